@@ -1,0 +1,275 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU).
+
+Each test checks the oracle against something other than itself: values the
+paper prints, exact rational arithmetic, closed forms, planted spectra,
+invariants, or an independent library routine.
+"""
+import csv
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute, eig, steps
+from paper_2006_08498_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows():
+    with open(os.path.join(GOLDEN, "eq_s1_tables.csv")) as f:
+        lines = [ln for ln in f if not ln.startswith("#")]
+    return list(csv.reader(lines))
+
+
+# ---------------------------------------------------------------- Eq. S1
+
+def test_eq_s1_interval_matches_tables_s8_s9():
+    rows = _rows()
+    assert len(rows) == 23
+    for r in rows:
+        lam, alpha, beta, c, e = map(float, r[2:7])
+        cc, ee = steps.interval(alpha, beta)
+        assert abs(cc - c) <= 6e-6 and abs(ee - e) <= 6e-6, r
+
+
+def test_eq_s1_rate_matches_tables_s8_s9():
+    for r in _rows():
+        lam, alpha, beta, c, e, inv_rho = map(float, r[2:8])
+        got = 1.0 / steps.rho(lam, c, e)
+        assert abs(got - inv_rho) <= 1.2e-5, (r, got)
+
+
+def test_eq_s1_rate_inside_interval_is_one():
+    assert steps.rho(5.0, 6.0, 2.0) == pytest.approx(1.0, abs=1e-15)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (5, 3), (6, 4), (8, 5)])
+def test_eigenvalues_match_exact_inertia_counts(N, seed):
+    A = synth.gaussian_integer_hermitian(N, seed)
+    exact = np.array(brute.eigenvalues(A.tolist()))
+    w, V = eig.eigh_lowest(A)
+    scale = max(1.0, np.abs(exact).max())
+    assert np.abs(w - exact).max() <= 1e-13 * scale
+
+
+def test_repeated_eigenvalues_exact():
+    B = synth.gaussian_integer_hermitian(3, 7)
+    A = np.kron(np.eye(2), B)                     # every eigenvalue twice
+    P = np.eye(6)[[3, 0, 4, 1, 5, 2]]              # mix the two copies
+    A = P @ A @ P.T
+    exact = np.array(brute.eigenvalues(A.tolist()))
+    assert np.allclose(exact[0::2], exact[1::2], atol=1e-14)
+    w, V = eig.eigh_lowest(A)
+    assert np.abs(w - exact).max() <= 1e-13 * max(1.0, np.abs(exact).max())
+    assert np.abs(V.conj().T @ V - np.eye(6)).max() <= 1e-13
+
+
+def test_rank_one_all_ones():
+    A = np.ones((4, 4), dtype=np.complex128)       # eigenvalues 0, 0, 0, 4
+    exact = brute.eigenvalues(A.tolist())
+    assert exact == pytest.approx([0, 0, 0, 4], abs=1e-15)
+    w, _ = eig.eigh_lowest(A)
+    assert w == pytest.approx([0, 0, 0, 4], abs=1e-14)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_two_by_two_closed_form():
+    a, d, b = 1.25, -0.5, 0.3 - 0.7j
+    A = np.array([[a, np.conj(b)], [b, d]])
+    m, r = 0.5 * (a + d), math.sqrt((0.5 * (a - d)) ** 2 + abs(b) ** 2)
+    w, V = eig.eigh_lowest(A)
+    assert w == pytest.approx([m - r, m + r], abs=1e-15)
+    assert np.abs(A @ V - V * w).max() <= 1e-15
+
+
+def test_diagonal_unsorted():
+    d = synth.dk_diag(40, seed=3)
+    w, V = eig.eigh_lowest(np.diag(d).astype(np.complex128), 7)
+    assert np.array_equal(w, np.sort(d)[:7])
+    for j in range(7):
+        k = np.argsort(d, kind="stable")[j]
+        assert abs(V[k, j]) == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("N", [17, 64, 150])
+def test_hermitian_circulant_fourier(N):
+    c = synth.hermitian_circulant_row(N, seed=N)
+    C = synth.circulant(c)
+    # Eigenvalue for Fourier vector f_k (f_k[i] = w^{ik}) is sum_m c_m w^{mk}.
+    lam = np.real(np.fft.ifft(c) * N)
+    w, V = eig.eigh_lowest(C, N)
+    assert np.abs(w - np.sort(lam)).max() <= 1e-12 * np.abs(lam).max()
+    # Lowest eigenvector: C v = lam v, and it lies in the span of the Fourier
+    # vectors with that eigenvalue.
+    k = int(np.argmin(lam))
+    f = np.exp(2j * np.pi * np.arange(N) * k / N) / math.sqrt(N)
+    same = np.abs(lam - lam[k]) <= 1e-9
+    F = np.exp(2j * np.pi * np.outer(np.arange(N), np.nonzero(same)[0]) / N) / math.sqrt(N)
+    v = V[:, 0]
+    assert np.linalg.norm(v - F @ (F.conj().T @ v)) <= 1e-10
+    assert np.linalg.norm(C @ f - lam[k] * f) <= 1e-11
+
+
+def test_tridiagonal_toeplitz():
+    N, a, b = 120, 2.0, 0.6 - 0.8j
+    T = synth.tridiag_toeplitz(N, a, b)
+    lam = a + 2 * abs(b) * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    w, V = eig.eigh_lowest(T, N)
+    assert np.abs(w - np.sort(lam)).max() <= 1e-13
+
+
+def test_real_tridiagonal_qr_closed_form():
+    n = 50
+    lam = 1.0 + 2 * 0.5 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    w, Z = eig.tridiag_eig(np.full(n, 1.0), np.full(n - 1, 0.5))
+    assert np.abs(w - np.sort(lam)).max() <= 1e-14
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-13
+
+
+# ---------------------------------------------------------------- planted
+
+def test_planted_spectrum_and_vectors():
+    N = 260
+    H, lam, Q = synth.planted_matrix(N, seed=1, n_clusters=5, cluster_size=4)
+    nev = 40
+    w, V = eig.eigh_lowest(H, nev)
+    assert np.abs(w - lam[:nev]).max() <= 1e-12 * lam.max()
+    # The first cluster is separated from the next by 0.025 - 3e-4: compare
+    # the cluster's invariant subspace (vectors within it are not unique).
+    P_or = V[:, :4] @ V[:, :4].conj().T
+    P_pl = Q[:, :4] @ Q[:, :4].conj().T
+    assert np.linalg.norm(P_or - P_pl, 2) <= 1e-10
+
+
+def test_invariants_dk_and_lapack_crosscheck():
+    N, nev = 500, 30
+    H = synth.dk_matrix(N, seed=2)
+    w, V = eig.eigh_lowest(H, nev)
+    hn = np.abs(np.linalg.eigvalsh(H)).max()
+    assert np.abs(H @ V - V * w).max() / hn <= 1e-13
+    assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-13
+    ref = np.linalg.eigvalsh(H)[:nev]        # independent library (LAPACK)
+    assert np.abs(w - ref).max() <= 1e-13 * hn
+    # Phase normalisation: entry of largest modulus real and positive.
+    for j in range(nev):
+        i = np.argmax(np.abs(V[:, j]))
+        assert V[i, j].imag == 0.0 and V[i, j].real > 0
+
+
+def test_only_lower_triangle_is_read():
+    H = synth.dk_matrix(60, seed=4)
+    G = np.tril(H) + np.triu(np.full((60, 60), 7.0 + 3.0j), 1)
+    w1, V1 = eig.eigh_lowest(H, 5)
+    w2, V2 = eig.eigh_lowest(G, 5)
+    assert np.array_equal(w1, w2) and np.array_equal(V1, V2)
+
+
+def test_eigenvalues_only_mode():
+    H = synth.dk_matrix(80, seed=5)
+    w1, _ = eig.eigh_lowest(H, 10, vectors=False)
+    w2, _ = eig.eigh_lowest(H, 10)
+    assert np.abs(w1 - w2).max() <= 1e-14
+
+
+# ---------------------------------------------------------------- steps
+
+def test_filter_matches_chebyshev_closed_form():
+    N = 90
+    H, lam, Q = synth.planted_matrix(N, seed=6, n_clusters=3, cluster_size=3)
+    V = synth.random_block(N, 6, seed=6)
+    mu1, alpha, beta = lam[0] - 0.01, lam[20], lam[-1] + 0.05
+    degrees = np.array([2, 4, 4, 6, 10, 20])
+    Y = steps.cheb_filter(H, V, degrees, mu1, alpha, beta)
+    c, e = steps.interval(alpha, beta)
+    t0 = (mu1 - c) / e
+    for j, m in enumerate(degrees):
+        f = steps.chebyshev_T(m, (lam - c) / e) / steps.chebyshev_T(m, np.array([t0]))[0]
+        ref = Q @ (f * (Q.conj().T @ V[:, j]))
+        assert np.linalg.norm(Y[:, j] - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_chebyshev_T_recurrence_values():
+    x = np.array([-3.0, -1.0, -0.3, 0.0, 0.7, 1.0, 2.5])
+    T0, T1 = np.ones_like(x), x.copy()
+    for m in range(2, 12):
+        T0, T1 = T1, 2 * x * T1 - T0
+        assert np.allclose(steps.chebyshev_T(m, x), T1, rtol=1e-12, atol=1e-12)
+
+
+def test_lanczos_two_by_two_by_hand():
+    a, b = 1.0, 3.0
+    H = np.diag([a, b]).astype(np.complex128)
+    v0 = np.array([[1.0], [1.0]], dtype=np.complex128)
+    al, be = steps.lanczos(H, v0, 2)
+    assert al[0, 0] == pytest.approx((a + b) / 2)
+    assert be[0, 0] == pytest.approx(abs(a - b) / 2)
+    # Second step: the Krylov space is all of C^2, so T's eigenvalues are a, b.
+    w, _ = eig.tridiag_eig(al[:, 0], be[:-1, 0])
+    assert w == pytest.approx([a, b], abs=1e-14)
+    assert be[1, 0] <= 1e-14
+
+
+def test_lanczos_bounds_bracket_spectrum():
+    N = 300
+    H = synth.dk_matrix(N, seed=7)
+    lam = np.linalg.eigvalsh(H)
+    V0 = synth.random_block(N, 4, seed=7)
+    al, be = steps.lanczos(H, V0, 25)
+    mu1, mu_ne, bsup, hnorm = steps.lanczos_bounds(al, be, N, 30)
+    assert bsup >= lam[-1]                       # upper bound of the spectrum
+    assert mu1 >= lam[0] - 1e-12                 # Ritz values interlace
+    assert mu1 - lam[0] <= 0.1 * (lam[-1] - lam[0])
+    assert hnorm <= np.abs(lam).max() + 1e-12
+    assert lam[0] <= mu_ne <= lam[-1]
+
+
+def test_degree_rule_is_minimal_steps():
+    c, e, tol = 6.0, 4.0, 1e-10
+    for lam, res in [(1.5, 1e-2), (1.9, 3e-4), (1.99, 0.5), (1.2, 1e-9)]:
+        m = steps.degree(res, tol, lam, c, e, degree_max=400, extra=0)
+        r = steps.rho(lam, c, e)
+        k = math.ceil(math.log(res / tol) / math.log(r))
+        assert r ** k >= res / tol > r ** (k - 1)
+        assert m == max(2, k + (k % 2))
+    assert steps.degree(1e-12, tol, 1.5, c, e, 20) == 2
+    assert steps.degree(1.0, tol, 2.5, c, e, 21) == 20    # inside: capped
+
+
+def test_qr_orth_definition():
+    V = synth.random_block(70, 9, seed=8)
+    Q = steps.qr_orth(V)
+    R = Q.conj().T @ V
+    assert np.abs(Q.conj().T @ Q - np.eye(9)).max() <= 1e-14
+    assert np.abs(np.tril(R, -1)).max() <= 1e-13
+    assert np.all(np.diag(R).real > 0) and np.abs(np.diag(R).imag).max() <= 1e-13
+
+
+def test_rayleigh_ritz_exact_invariant_subspace():
+    N = 120
+    H, lam, Q = synth.planted_matrix(N, seed=9, n_clusters=2, cluster_size=5)
+    pick = [0, 3, 7, 11, 50]
+    Z = synth.random_block(5, 5, seed=9)
+    U, _ = np.linalg.qr(Z)
+    B = Q[:, pick] @ U                            # rotated invariant subspace
+    theta, V, _ = steps.rayleigh_ritz(H, B)
+    assert np.abs(theta - lam[pick]).max() <= 1e-13 * lam.max()
+    assert steps.residual_norms(H, V, theta).max() <= 1e-12
+
+
+def test_residual_of_two_eigenvector_mix():
+    N = 50
+    H, lam, Q = synth.planted_matrix(N, seed=10, n_clusters=0, cluster_size=0)
+    v = (Q[:, 0] + Q[:, 5]) / math.sqrt(2)
+    th = 0.5 * (lam[0] + lam[5])
+    r = steps.residual_norms(H, v[:, None], [th])[0]
+    assert r == pytest.approx(0.5 * abs(lam[5] - lam[0]), rel=1e-12)
+
+
+def test_lock_count_prefix_only():
+    assert steps.lock_count([1e-12, 1e-11, 1e-3, 1e-12], 1e-10) == 2
+    assert steps.lock_count([1e-3, 1e-12], 1e-10) == 0
