@@ -1,0 +1,253 @@
+/*
+ * chase_mi355x.h -- C ABI of an MI355X (gfx950) implementation of ChASE,
+ * the Chebyshev Accelerated Subspace iteration Eigensolver used by the
+ * modernised Bethe-Salpeter (BSE) solver of Zhang et al., "Solving the
+ * Bethe-Salpeter equation on massively parallel architectures"
+ * (arXiv:2006.08498).
+ *
+ * The solver finds the nev algebraically smallest eigenvalues and their
+ * eigenvectors of a dense complex Hermitian matrix H of order N (the
+ * low-lying excitons; the paper wants full eigenpairs, not eigenvalues
+ * only: Sec. "Solving the BSE eigenvalue problem on massively parallel
+ * architectures").  nex extra vectors enlarge the search subspace to
+ * nev + nex columns (same section; its size changes convergence, supplement
+ * Sec. "Dependence of the convergence rate of ChASE on nex").  The phases
+ * follow the supplement's list: Lanczos (spectral estimates), Filter
+ * (Chebyshev three-term recurrence as repeated HEMM), QR, RR (Rayleigh-Ritz)
+ * and Resid (residuals, deflation and locking).
+ *
+ * Conventions for every call below.
+ *  - Pointers named d* are device pointers, h* are host pointers.  The
+ *    caller owns all memory passed in; the library never frees it.
+ *  - H is complex128, column-major, element (i, j) at dH[i + j*ldh],
+ *    ldh >= N, both triangles stored and Hermitian.  H is never written.
+ *    (A row-major Hermitian array read as column-major is conj(H) = H^T:
+ *    same eigenvalues, conjugated eigenvectors.)
+ *  - Eigenvector outputs of the solve calls are column-major N x nev with
+ *    leading dimension ldv >= N.  Step-level calls (below the solve calls)
+ *    take vector blocks in the solver's internal layout: row-major, element
+ *    (i, j) of an N x n block at p[i*ld + j], ld >= n.
+ *  - stream is a hipStream_t (NULL = the null stream).  Every call returns
+ *    after its work on that stream has completed.
+ *  - Status codes are returned; nothing throws across the ABI.  Arguments
+ *    are validated before any device work.  On failure chase_last_error()
+ *    returns a message (thread-local, valid until the next call on the same
+ *    thread).
+ *  - Calls on different streams from different threads are re-entrant.
+ *  - Results are deterministic: the same inputs, options and seed give the
+ *    same bits (no atomics in reductions, fixed reduction order).
+ */
+#ifndef CHASE_MI355X_H
+#define CHASE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* complex128, layout-compatible with std::complex<double> and numpy/torch
+ * complex128 */
+typedef struct { double re, im; } chase_z;
+
+enum chase_status {
+    CHASE_PENDING = -1,    /* server: request not finished yet */
+    CHASE_OK = 0,
+    CHASE_EINVAL = 1,      /* invalid argument */
+    CHASE_ENOMEM = 2,      /* device allocation or workspace too small */
+    CHASE_EHIP = 3,        /* HIP runtime error */
+    CHASE_ENOCONV = 4,     /* max_iter reached; outputs hold the best pairs */
+    CHASE_ENONFINITE = 5,  /* NaN/Inf met (e.g. in H) */
+    CHASE_EBOUNDS = 6,     /* a Ritz value exceeded the spectral upper bound */
+    CHASE_EINTERNAL = 7
+};
+
+enum chase_precision {
+    CHASE_FP64 = 0,        /* every phase in FP64 */
+    CHASE_MIXED = 1        /* filter in FP32 while a vector's residual is
+                              above switch_tol, FP64 afterwards */
+};
+
+typedef struct chase_opts {
+    int32_t precision;        /* chase_precision; default CHASE_FP64 */
+    int32_t max_iter;         /* subspace iterations; default 100 */
+    int32_t initial_degree;   /* filter degree of the first iteration;
+                                 default 20 (capped by degree_max) */
+    int32_t degree_extra;     /* steps added to each computed degree;
+                                 default 2 */
+    int32_t lanczos_steps;    /* Lanczos steps per run; default 25 */
+    int32_t lanczos_runs;     /* independent Lanczos runs; default 4 */
+    uint64_t seed;            /* start vectors (Philox4x32-10); default 0 */
+    double switch_tol;        /* CHASE_MIXED: residual / ||H|| above which a
+                                 vector is filtered in FP32; default 1e-5 */
+    const chase_z *dV0;       /* optional warm start, N x (nev+nex),
+                                 column-major, leading dimension N; NULL =
+                                 random start */
+    int32_t profile;          /* 1: time every filter launch with HIP events
+                                 (fills t_filter_kernels) */
+    int32_t reserved[7];
+} chase_opts;
+
+typedef struct chase_info {
+    int32_t iterations;        /* subspace iterations done */
+    int32_t nconv;             /* converged (locked) eigenpairs */
+    int64_t matvecs_filter;    /* filter column products (H times one
+                                  column), the paper's mat-vec count */
+    int64_t matvecs_filter_fp32; /* of which in FP32 (CHASE_MIXED) */
+    int64_t matvecs_total;     /* filter + Rayleigh-Ritz + Lanczos */
+    int64_t filter_launches;   /* filter kernel launches */
+    double mu1;                /* lower spectral estimate */
+    double mu_ne;              /* Lanczos estimate of lambda_{nev+nex} */
+    double alpha;              /* lower end of the damped interval, last
+                                  iteration */
+    double beta;               /* upper end (spectral upper bound) */
+    double hnorm_est;          /* estimate of ||H||_2 used by the tolerance */
+    double t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds */
+    double t_filter_kernels;   /* sum of filter kernel durations (profile) */
+    double filter_flops;       /* algorithmic filter flops, 8 N^2 per
+                                  column product */
+} chase_info;
+
+/* Fills *o with the defaults listed above. */
+void chase_default_opts(chase_opts *o);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *chase_last_error(void);
+
+/* ------------------------------------------------------------------ solve */
+
+/*
+ * Lowest nev eigenpairs of H to residual tolerance tol: every returned pair
+ * satisfies ||H v - lambda v||_2 <= tol * ||H||_2 (||H||_2 estimated from
+ * below by the Lanczos phase).  h_eigvals: nev doubles, ascending.  dV:
+ * N x nev, column-major, leading dimension N, orthonormal columns; in each
+ * column the entry of largest modulus (lowest index on ties) is real and
+ * positive.  Requires 1 <= nev, 0 <= nex, nev + nex <= N, tol > 0,
+ * nev + nex <= 1024 (with nex = 0 and nev < N one extra search vector is
+ * carried internally: without it the top wanted vector cannot converge),
+ * 2 <= degree_max <= 64 (degrees are even; an odd degree_max acts as
+ * degree_max - 1).  Allocates its own workspace; runs on the null stream.
+ */
+int chase_solve(const chase_z *dH, int64_t N, int32_t nev, int32_t nex,
+                double tol, int32_t degree_max,
+                double *h_eigvals, chase_z *dV);
+
+/* Bytes of device workspace chase_solve_ex needs for these sizes. */
+size_t chase_workspace_bytes(int64_t N, int32_t nev, int32_t nex,
+                             const chase_opts *o);
+
+/*
+ * Full form.  h_resid (nev doubles, may be NULL) receives the residual norms
+ * ||H v_j - lambda_j v_j||_2.  dwork/work_bytes: caller-provided device
+ * workspace of at least chase_workspace_bytes() bytes, 256-byte aligned, or
+ * NULL/0 to let the library allocate.  o == NULL means defaults.  info may
+ * be NULL.  On CHASE_ENOCONV the outputs hold the current best Ritz pairs
+ * and info->nconv < nev.
+ */
+int chase_solve_ex(const chase_z *dH, int64_t N, int64_t ldh,
+                   int32_t nev, int32_t nex, double tol, int32_t degree_max,
+                   double *h_eigvals, double *h_resid,
+                   chase_z *dV, int64_t ldv,
+                   void *dwork, size_t work_bytes,
+                   void *stream, const chase_opts *o, chase_info *info);
+
+/* ------------------------------------------------------- step-level calls
+ * One phase each, on caller-provided blocks (row-major, see above).  They
+ * allocate any scratch they need. */
+
+/*
+ * One Chebyshev recurrence step over ncols columns (Filter phase, one HEMM
+ * with the recurrence folded into its epilogue):
+ *     W = a * H Y + b * Y + g * X.
+ * dX may be NULL when g == 0.  dW may equal dX (in-place update of the
+ * older iterate); dW must not overlap dY.
+ */
+int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
+                      const chase_z *dY, int64_t ldy,
+                      const chase_z *dX, int64_t ldx,
+                      chase_z *dW, int64_t ldw, int32_t ncols,
+                      double a, double b, double g, void *stream);
+
+/*
+ * The whole Chebyshev filter with per-vector degrees on an N x n block,
+ * in place: column j becomes C_m(L) v_j / C_m(t0), m = h_degrees[j],
+ * L = (H - cI)/e, t0 = (mu1 - c)/e, c = (alpha+beta)/2, e = (beta-alpha)/2.
+ * h_degrees: n even integers >= 2, ascending.  Returns the number of
+ * column products in *matvecs (may be NULL).
+ */
+int chase_filter(const chase_z *dH, int64_t N, int64_t ldh,
+                 chase_z *dV, int64_t ldv, int32_t n,
+                 const int32_t *h_degrees, double mu1, double alpha,
+                 double beta, int64_t *matvecs, void *stream);
+
+/*
+ * k Lanczos steps from each of the r columns of dV0 (N x r, need not be
+ * normalised; not modified).  h_alpha, h_beta: k*r doubles each, row-major
+ * [step][run]; T of run q is tridiag(alpha[:, q]; beta[0:k-1, q]) and
+ * beta[k-1, q] is the norm of the last residual.
+ */
+int chase_lanczos(const chase_z *dH, int64_t N, int64_t ldh,
+                  const chase_z *dV0, int64_t ldv0, int32_t r, int32_t k,
+                  double *h_alpha, double *h_beta, void *stream);
+
+/*
+ * Spectral estimates from Lanczos output (host only): out[0] = mu1
+ * (smallest Ritz value), out[1] = mu_ne (spectral-density estimate of
+ * lambda_ne), out[2] = upper bound (largest Ritz value + last beta, max over
+ * runs), out[3] = largest |Ritz value| (estimate of ||H||_2 from below).
+ */
+int chase_lanczos_bounds(const double *h_alpha, const double *h_beta,
+                         int32_t k, int32_t r, int64_t N, int32_t ne,
+                         double *out4);
+
+/*
+ * QR phase: orthonormalise columns [nlocked, n) of the N x n block dV in
+ * place, against the (orthonormal, unchanged) columns [0, nlocked) and
+ * among themselves, so that span is kept: two classical Gram-Schmidt passes
+ * against the locked columns, then shifted CholeskyQR3 with column
+ * scaling.  The result equals Q of V_active = Q R with diag(R) > 0.
+ */
+int chase_qr(chase_z *dV, int64_t N, int64_t ldv, int32_t n,
+             int32_t nlocked, void *stream);
+
+/*
+ * RR phase on the orthonormal N x n block dQ: G = Q^H H Q, G = Y Theta Y^H
+ * (Theta ascending), Q <- Q Y in place.  h_theta: n doubles.  If h_resid is
+ * not NULL it receives ||H q_j - theta_j q_j||_2 (Resid phase).
+ */
+int chase_rayleigh_ritz(const chase_z *dH, int64_t N, int64_t ldh,
+                        chase_z *dQ, int64_t ldq, int32_t n,
+                        double *h_theta, double *h_resid, void *stream);
+
+/*
+ * Resid phase: h_resid[j] = ||H v_j - h_theta[j] v_j||_2 for the N x n
+ * block dV.
+ */
+int chase_residuals(const chase_z *dH, int64_t N, int64_t ldh,
+                    const chase_z *dV, int64_t ldv, int32_t n,
+                    const double *h_theta, double *h_resid, void *stream);
+
+/*
+ * Dense Hermitian eigensolver for the reduced problem (on the device,
+ * cyclic Jacobi): dG n x n row-major (leading dimension n), not modified;
+ * h_w: n eigenvalues ascending; dY: n x n row-major eigenvectors (columns).
+ */
+int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
+                void *stream);
+
+/*
+ * Filter degrees (host only): for each of n vectors with Ritz value
+ * h_theta[j] and residual h_resid[j], the smallest m with
+ * rho_j^m >= resid_j / tol_abs (rho_j of the supplement's Eq. S1 on the
+ * interval [alpha, beta]) plus extra, clamped to [2, degree_max] and made
+ * even; 2 for converged vectors.
+ */
+int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
+                  double tol_abs, double alpha, double beta,
+                  int32_t degree_max, int32_t extra, int32_t *h_degrees);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHASE_MI355X_H */

@@ -1,0 +1,358 @@
+"""Python binding of libchase_mi355x (argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels; torch provides
+device memory and the stream.  The binding fails loudly when the library
+is missing: there is no CPU fallback.
+
+Layout of H: the C ABI reads H column-major.  A torch tensor with strides
+(1, N) is passed as is.  A row-major tensor (strides (N, 1)) read
+column-major is H^T = conj(H) for a Hermitian H: the eigenvalues are the
+same and the eigenvectors are conjugated, which the binding undoes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchase_mi355x.so")
+
+CHASE_PENDING = -1
+CHASE_OK = 0
+CHASE_EINVAL = 1
+CHASE_ENOMEM = 2
+CHASE_EHIP = 3
+CHASE_ENOCONV = 4
+CHASE_ENONFINITE = 5
+CHASE_EBOUNDS = 6
+CHASE_EINTERNAL = 7
+CHASE_FP64 = 0
+CHASE_MIXED = 1
+
+STATUS_NAMES = {
+    CHASE_PENDING: "CHASE_PENDING", CHASE_OK: "CHASE_OK",
+    CHASE_EINVAL: "CHASE_EINVAL", CHASE_ENOMEM: "CHASE_ENOMEM",
+    CHASE_EHIP: "CHASE_EHIP", CHASE_ENOCONV: "CHASE_ENOCONV",
+    CHASE_ENONFINITE: "CHASE_ENONFINITE", CHASE_EBOUNDS: "CHASE_EBOUNDS",
+    CHASE_EINTERNAL: "CHASE_EINTERNAL",
+}
+
+
+class ChaseOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("initial_degree", ctypes.c_int32),
+        ("degree_extra", ctypes.c_int32),
+        ("lanczos_steps", ctypes.c_int32),
+        ("lanczos_runs", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("switch_tol", ctypes.c_double),
+        ("dV0", ctypes.c_void_p),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class ChaseInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("nconv", ctypes.c_int32),
+        ("matvecs_filter", ctypes.c_int64),
+        ("matvecs_filter_fp32", ctypes.c_int64),
+        ("matvecs_total", ctypes.c_int64),
+        ("filter_launches", ctypes.c_int64),
+        ("mu1", ctypes.c_double),
+        ("mu_ne", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("hnorm_est", ctypes.c_double),
+        ("t_lanczos", ctypes.c_double),
+        ("t_filter", ctypes.c_double),
+        ("t_qr", ctypes.c_double),
+        ("t_rr", ctypes.c_double),
+        ("t_resid", ctypes.c_double),
+        ("t_total", ctypes.c_double),
+        ("t_filter_kernels", ctypes.c_double),
+        ("filter_flops", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ChaseError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+# Exported symbols and their signatures (must match include/chase_mi355x.h).
+SIGNATURES = {
+    "chase_default_opts": (None, [ctypes.POINTER(ChaseOpts)]),
+    "chase_last_error": (ctypes.c_char_p, []),
+    "chase_solve": (ctypes.c_int, [_P, _I64, _I32, _I32, _D, _I32, _P, _P]),
+    "chase_workspace_bytes": (ctypes.c_size_t, [_I64, _I32, _I32, ctypes.POINTER(ChaseOpts)]),
+    "chase_solve_ex": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, _D, _I32, _P, _P,
+                                      _P, _I64, _P, ctypes.c_size_t, _P,
+                                      ctypes.POINTER(ChaseOpts), ctypes.POINTER(ChaseInfo)]),
+    "chase_filter_step": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
+                                         _I32, _D, _D, _D, _P]),
+    "chase_filter": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _D, _D, _D,
+                                    ctypes.POINTER(ctypes.c_int64), _P]),
+    "chase_lanczos": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _P, _P, _P]),
+    "chase_lanczos_bounds": (ctypes.c_int, [_P, _P, _I32, _I32, _I64, _I32, _P]),
+    "chase_qr": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, _P]),
+    "chase_rayleigh_ritz": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _P, _P]),
+    "chase_residuals": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _P, _P]),
+    "chase_heevj": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
+    "chase_degrees": (ctypes.c_int, [_P, _P, _I32, _D, _D, _D, _I32, _I32, _P]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python paper_2006_08498_amd/build.py` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    msg = lib().chase_last_error()
+    return msg.decode() if msg else ""
+
+
+def _check(st, allow=(CHASE_OK,)):
+    if st not in allow:
+        raise ChaseError(st, last_error())
+    return st
+
+
+def default_opts(**kw) -> ChaseOpts:
+    o = ChaseOpts()
+    lib().chase_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+# ------------------------------------------------------------------ torch
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _h_layout(H):
+    """(pointer, ldh, conjugated?) for a square complex128 CUDA tensor."""
+    torch = _torch()
+    if H.dtype != torch.complex128 or not H.is_cuda or H.dim() != 2:
+        raise ValueError("H must be a 2-D complex128 CUDA tensor")
+    N = H.shape[0]
+    if H.shape[1] != N:
+        raise ValueError("H must be square")
+    s0, s1 = H.stride()
+    if s0 == 1 and s1 >= N:
+        return _dptr(H), s1, False
+    if s1 == 1 and s0 >= N:
+        return _dptr(H), s0, True
+    raise ValueError("H must be column-major (strides (1, ld)) or row-major (ld, 1)")
+
+
+@dataclass
+class SolveResult:
+    eigvals: np.ndarray
+    V: object                 # torch (N, nev) complex128 on the device
+    resid: np.ndarray
+    status: int
+    info: dict = field(default_factory=dict)
+
+
+def workspace_bytes(N, nev, nex, opts=None) -> int:
+    o = opts if opts is not None else default_opts()
+    return int(lib().chase_workspace_bytes(N, nev, nex, ctypes.byref(o)))
+
+
+def solve(H, nev, nex, tol=1e-10, degree_max=20, *, opts=None, V0=None,
+          workspace=None, stream=None, allow_noconv=False, **opt_kw):
+    """Lowest ``nev`` eigenpairs of the Hermitian CUDA tensor ``H``.
+
+    Returns eigenvalues (ascending), eigenvectors as an (N, nev) tensor,
+    residual norms, the status and the solver's info record."""
+    torch = _torch()
+    N = H.shape[0]
+    hp, ldh, conj = _h_layout(H)
+    o = opts if opts is not None else default_opts(**opt_kw)
+    v0_keep = None
+    if V0 is not None:
+        # Warm start, N x (nev+nex): the ABI wants it column-major (and
+        # conjugated when H is passed row-major, i.e. as conj(H)).
+        v0 = V0.conj() if conj else V0
+        v0_keep = v0.t().contiguous()       # (ne, N) row-major == col-major
+        o.dV0 = v0_keep.data_ptr()
+    out = torch.empty((nev, N), dtype=torch.complex128, device=H.device)
+    ev = np.zeros(nev, dtype=np.float64)
+    rs = np.zeros(nev, dtype=np.float64)
+    info = ChaseInfo()
+    wptr, wbytes = None, 0
+    if workspace is not None:
+        wptr, wbytes = _dptr(workspace), workspace.numel() * workspace.element_size()
+    st = lib().chase_solve_ex(
+        hp, N, ldh, nev, nex, tol, degree_max,
+        ev.ctypes.data_as(_P), rs.ctypes.data_as(_P), _dptr(out), N,
+        wptr, wbytes, _stream_ptr(stream), ctypes.byref(o), ctypes.byref(info))
+    _check(st, (CHASE_OK, CHASE_ENOCONV) if allow_noconv else (CHASE_OK,))
+    V = out.t()
+    if conj:
+        V = V.conj().resolve_conj()
+    del v0_keep
+    return SolveResult(ev, V, rs, st, info.as_dict())
+
+
+# ------------------------------------------------------------ step level
+# Vector blocks are row-major (N, n) contiguous torch tensors.
+
+def _block(t, name):
+    torch = _torch()
+    if t.dtype != torch.complex128 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major complex128 CUDA block")
+    return _dptr(t), t.stride(0)
+
+
+def _h_colmajor(H):
+    hp, ldh, conj = _h_layout(H)
+    if conj:
+        raise ValueError("step-level calls take H column-major (strides (1, ld))")
+    return hp, ldh
+
+
+def filter_step(H, Y, X, a, b, g, W=None, stream=None):
+    """W = a H Y + b Y + g X (W defaults to a new block; may be X)."""
+    torch = _torch()
+    hp, ldh = _h_colmajor(H)
+    N, n = Y.shape
+    yp, ldy = _block(Y, "Y")
+    xp, ldx = _block(X, "X") if X is not None else (None, n)
+    if W is None:
+        W = torch.empty_like(Y)
+    wp, ldw = _block(W, "W")
+    _check(lib().chase_filter_step(hp, N, ldh, yp, ldy, xp, ldx, wp, ldw, n,
+                                   a, b, g, _stream_ptr(stream)))
+    return W
+
+
+def filter(H, V, degrees, mu1, alpha, beta, stream=None):
+    """Per-vector-degree Chebyshev filter of V in place; returns mat-vecs."""
+    hp, ldh = _h_colmajor(H)
+    N, n = V.shape
+    vp, ldv = _block(V, "V")
+    deg = np.ascontiguousarray(degrees, dtype=np.int32)
+    mv = ctypes.c_int64(0)
+    _check(lib().chase_filter(hp, N, ldh, vp, ldv, n, deg.ctypes.data_as(_P),
+                              mu1, alpha, beta, ctypes.byref(mv), _stream_ptr(stream)))
+    return int(mv.value)
+
+
+def lanczos(H, V0, k, stream=None):
+    """(alpha[k, r], beta[k, r]) of k Lanczos steps from the columns of V0."""
+    hp, ldh = _h_colmajor(H)
+    N, r = V0.shape
+    vp, ldv = _block(V0, "V0")
+    al = np.zeros((k, r))
+    be = np.zeros((k, r))
+    _check(lib().chase_lanczos(hp, N, ldh, vp, ldv, r, k, al.ctypes.data_as(_P),
+                               be.ctypes.data_as(_P), _stream_ptr(stream)))
+    return al, be
+
+
+def lanczos_bounds(al, be, N, ne):
+    al = np.ascontiguousarray(al, dtype=np.float64)
+    be = np.ascontiguousarray(be, dtype=np.float64)
+    k, r = al.shape
+    out = np.zeros(4)
+    _check(lib().chase_lanczos_bounds(al.ctypes.data_as(_P), be.ctypes.data_as(_P),
+                                      k, r, N, ne, out.ctypes.data_as(_P)))
+    return tuple(float(x) for x in out)
+
+
+def qr(V, nlocked=0, stream=None):
+    N, n = V.shape
+    vp, ldv = _block(V, "V")
+    _check(lib().chase_qr(vp, N, ldv, n, nlocked, _stream_ptr(stream)))
+    return V
+
+
+def rayleigh_ritz(H, Q, stream=None, residuals=True):
+    hp, ldh = _h_colmajor(H)
+    N, n = Q.shape
+    qp, ldq = _block(Q, "Q")
+    th = np.zeros(n)
+    rs = np.zeros(n) if residuals else None
+    _check(lib().chase_rayleigh_ritz(hp, N, ldh, qp, ldq, n, th.ctypes.data_as(_P),
+                                     rs.ctypes.data_as(_P) if residuals else None,
+                                     _stream_ptr(stream)))
+    return th, rs
+
+
+def residuals(H, V, theta, stream=None):
+    hp, ldh = _h_colmajor(H)
+    N, n = V.shape
+    vp, ldv = _block(V, "V")
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    rs = np.zeros(n)
+    _check(lib().chase_residuals(hp, N, ldh, vp, ldv, n, th.ctypes.data_as(_P),
+                                 rs.ctypes.data_as(_P), _stream_ptr(stream)))
+    return rs
+
+
+def heevj(G, stream=None):
+    """Eigen-decomposition of a small Hermitian (n, n) row-major CUDA tensor."""
+    torch = _torch()
+    n = G.shape[0]
+    gp, ldg = _block(G, "G")
+    if ldg != n:
+        raise ValueError("G must be contiguous")
+    Y = torch.empty_like(G)
+    w = np.zeros(n)
+    _check(lib().chase_heevj(gp, n, w.ctypes.data_as(_P), _dptr(Y), _stream_ptr(stream)))
+    return w, Y
+
+
+def degrees(theta, resid, tol_abs, alpha, beta, degree_max, extra=2):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    rs = np.ascontiguousarray(resid, dtype=np.float64)
+    out = np.zeros(th.size, dtype=np.int32)
+    _check(lib().chase_degrees(th.ctypes.data_as(_P), rs.ctypes.data_as(_P), th.size,
+                               tol_abs, alpha, beta, degree_max, extra,
+                               out.ctypes.data_as(_P)))
+    return out

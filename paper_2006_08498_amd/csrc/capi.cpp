@@ -1,0 +1,436 @@
+// C ABI of libchase_mi355x: validation, workspace handling, status codes.
+// No exception crosses this boundary.
+#include "../../include/chase_mi355x.h"
+
+#include "common.h"
+#include "control.h"
+#include "solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace chase;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int st, const std::string &m) {
+    g_err = m;
+    return st;
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const Error &e) {
+        return fail(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(CHASE_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(CHASE_EINTERNAL, e.what());
+    } catch (...) {
+        return fail(CHASE_EINTERNAL, "unknown error");
+    }
+}
+
+#define REQUIRE(cond, msg) \
+    do {                   \
+        if (!(cond)) throw Error(CHASE_EINVAL, msg); \
+    } while (0)
+
+// Device buffer released on scope exit (after the stream has drained).
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf(size_t bytes, hipStream_t st) : s(st) {
+        if (bytes == 0) return;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(CHASE_ENOMEM, "hipMalloc of " + std::to_string(bytes) +
+                                          " bytes failed: " + hipGetErrorString(e));
+        }
+    }
+    ~DevBuf() {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    }
+    template <class T>
+    T *as(size_t byte_off = 0) const {
+        return reinterpret_cast<T *>(static_cast<char *>(p) + byte_off);
+    }
+};
+
+hipStream_t S(void *stream) { return reinterpret_cast<hipStream_t>(stream); }
+
+void validate_sizes(int64_t N, int32_t nev, int32_t nex) {
+    REQUIRE(N >= 1, "N must be >= 1");
+    REQUIRE(N <= (int64_t)1 << 31, "N too large for 32-bit row indices");
+    REQUIRE(nev >= 1, "nev must be >= 1");
+    REQUIRE(nex >= 0, "nex must be >= 0");
+    REQUIRE((int64_t)nev + nex <= N, "nev + nex must be <= N");
+    REQUIRE(nev + nex <= 1024, "nev + nex must be <= 1024");
+}
+
+chase_opts resolve(const chase_opts *o) {
+    chase_opts r;
+    chase_default_opts(&r);
+    if (o) r = *o;
+    return r;
+}
+
+void validate_opts(const chase_opts &o) {
+    REQUIRE(o.precision == CHASE_FP64 || o.precision == CHASE_MIXED,
+            "unknown precision");
+    REQUIRE(o.precision == CHASE_FP64, "CHASE_MIXED is not available in this build");
+    REQUIRE(o.max_iter >= 1, "max_iter must be >= 1");
+    REQUIRE(o.initial_degree >= 1, "initial_degree must be >= 1");
+    REQUIRE(o.degree_extra >= 0, "degree_extra must be >= 0");
+    REQUIRE(o.lanczos_steps >= 1, "lanczos_steps must be >= 1");
+    REQUIRE(o.lanczos_runs >= 1 && o.lanczos_runs <= 64, "lanczos_runs must be in [1, 64]");
+    REQUIRE(o.switch_tol > 0.0, "switch_tol must be > 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+void chase_default_opts(chase_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = CHASE_FP64;
+    o->max_iter = 100;
+    o->initial_degree = 20;
+    o->degree_extra = 2;
+    o->lanczos_steps = 25;
+    o->lanczos_runs = 4;
+    o->seed = 0;
+    o->switch_tol = 1e-5;
+    o->dV0 = nullptr;
+    o->profile = 0;
+}
+
+const char *chase_last_error(void) { return g_err.c_str(); }
+
+size_t chase_workspace_bytes(int64_t N, int32_t nev, int32_t nex,
+                             const chase_opts *o) {
+    if (N < 1 || nev < 1 || nex < 0 || (int64_t)nev + nex > N) return 0;
+    const chase_opts r = resolve(o);
+    return make_layout(N, nev, nex, r).total;
+}
+
+int chase_solve_ex(const chase_z *dH, int64_t N, int64_t ldh, int32_t nev,
+                   int32_t nex, double tol, int32_t degree_max,
+                   double *h_eigvals, double *h_resid, chase_z *dV,
+                   int64_t ldv, void *dwork, size_t work_bytes, void *stream,
+                   const chase_opts *o, chase_info *info) {
+    return guarded([&]() -> int {
+        validate_sizes(N, nev, nex);
+        REQUIRE(dH != nullptr, "dH is NULL");
+        REQUIRE(ldh >= N, "ldh must be >= N");
+        REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be > 0");
+        REQUIRE(degree_max >= 2 && degree_max <= 64, "degree_max must be in [2, 64]");
+        REQUIRE(h_eigvals != nullptr, "h_eigvals is NULL");
+        REQUIRE(dV != nullptr, "dV is NULL");
+        REQUIRE(ldv >= N, "ldv must be >= N");
+        const chase_opts opts = resolve(o);
+        validate_opts(opts);
+        const Layout lay = make_layout(N, nev, nex, opts);
+        hipStream_t s = S(stream);
+        DevBuf own(dwork ? 0 : lay.total, s);
+        void *ws = dwork;
+        if (dwork) {
+            if (work_bytes < lay.total)
+                throw Error(CHASE_ENOMEM, "workspace too small: need " +
+                                              std::to_string(lay.total) + " bytes");
+            REQUIRE(((uintptr_t)dwork & 255) == 0, "workspace must be 256-byte aligned");
+        } else {
+            ws = own.p;
+        }
+        Problem p{reinterpret_cast<const Z *>(dH), N, ldh, nev, nex, tol, degree_max, opts};
+        Result R = solve(p, ws, reinterpret_cast<Z *>(dV), ldv, s);
+        std::copy(R.eigvals.begin(), R.eigvals.end(), h_eigvals);
+        if (h_resid) std::copy(R.resid.begin(), R.resid.end(), h_resid);
+        if (info) *info = R.info;
+        if (R.status == CHASE_ENOCONV)
+            g_err = "not converged after max_iter iterations (" +
+                    std::to_string(R.info.nconv) + " of " + std::to_string(nev) + ")";
+        return R.status;
+    });
+}
+
+int chase_solve(const chase_z *dH, int64_t N, int32_t nev, int32_t nex,
+                double tol, int32_t degree_max, double *h_eigvals,
+                chase_z *dV) {
+    return chase_solve_ex(dH, N, N, nev, nex, tol, degree_max, h_eigvals,
+                          nullptr, dV, N, nullptr, 0, nullptr, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------ step level
+
+int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
+                      const chase_z *dY, int64_t ldy, const chase_z *dX,
+                      int64_t ldx, chase_z *dW, int64_t ldw, int32_t ncols,
+                      double a, double b, double g, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "bad N");
+        REQUIRE(ncols >= 0, "ncols must be >= 0");
+        REQUIRE(dH && dY && dW, "NULL pointer");
+        REQUIRE(g == 0.0 || dX, "dX is NULL while g != 0");
+        REQUIRE(ldh >= N && ldy >= ncols && ldw >= ncols && (!dX || ldx >= ncols),
+                "bad leading dimension");
+        if (ncols == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        DevBuf part(filter_partial_elems(N, ncols) * sizeof(Z), s);
+        filter_gemm(reinterpret_cast<const Z *>(dH), ldh, N,
+                    reinterpret_cast<const Z *>(dY), ldy,
+                    reinterpret_cast<const Z *>(dX), ldx,
+                    reinterpret_cast<Z *>(dW), ldw, ncols, a, b, g,
+                    part.as<Z>(), s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_filter(const chase_z *dH, int64_t N, int64_t ldh, chase_z *dV,
+                 int64_t ldv, int32_t n, const int32_t *h_degrees, double mu1,
+                 double alpha, double beta, int64_t *matvecs, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "bad N");
+        REQUIRE(n >= 0 && ldv >= n && ldh >= N, "bad sizes");
+        REQUIRE(dH && dV && (n == 0 || h_degrees), "NULL pointer");
+        REQUIRE(beta > alpha && mu1 < alpha, "need mu1 < alpha < beta");
+        int64_t mv = 0;
+        for (int j = 0; j < n; ++j) {
+            REQUIRE(h_degrees[j] >= 2 && h_degrees[j] % 2 == 0 && h_degrees[j] <= 64,
+                    "degrees must be even, in [2, 64]");
+            REQUIRE(j == 0 || h_degrees[j] >= h_degrees[j - 1], "degrees must be ascending");
+            mv += h_degrees[j];
+        }
+        if (matvecs) *matvecs = mv;
+        if (n == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        size_t fp = 0;
+        for (int c = 1; c <= n; ++c) fp = std::max(fp, filter_partial_elems(N, c));
+        const size_t blk = (size_t)N * n * sizeof(Z);
+        DevBuf buf(blk + fp * sizeof(Z) + 256, s);
+        Z *B1 = buf.as<Z>();
+        Z *part = buf.as<Z>((blk + 255) & ~size_t(255));
+        // Work on a compact copy so the caller's leading dimension is free.
+        DevBuf vb(blk, s);
+        Z *Vc = vb.as<Z>();
+        copy_block(reinterpret_cast<Z *>(dV), ldv, Vc, n, N, n, s);
+        filter_block(reinterpret_cast<const Z *>(dH), ldh, N, Vc, B1, n, n,
+                     h_degrees, mu1, alpha, beta, part, s, nullptr);
+        copy_block(Vc, n, reinterpret_cast<Z *>(dV), ldv, N, n, s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_lanczos(const chase_z *dH, int64_t N, int64_t ldh,
+                  const chase_z *dV0, int64_t ldv0, int32_t r, int32_t k,
+                  double *h_alpha, double *h_beta, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31 && ldh >= N, "bad N/ldh");
+        REQUIRE(r >= 1 && r <= 64 && k >= 1 && ldv0 >= r, "bad r/k/ldv0");
+        REQUIRE(dH && dV0 && h_alpha && h_beta, "NULL pointer");
+        hipStream_t s = S(stream);
+        const size_t vb = (size_t)N * r * sizeof(Z);
+        const size_t fp = filter_partial_elems(N, r) * sizeof(Z);
+        DevBuf buf(3 * vb + fp + 2 * (size_t)k * r * sizeof(double) + 1024, s);
+        char *b = buf.as<char>();
+        Z *v = reinterpret_cast<Z *>(b);
+        Z *vp = reinterpret_cast<Z *>(b + vb);
+        Z *w = reinterpret_cast<Z *>(b + 2 * vb);
+        double *al = reinterpret_cast<double *>(b + 3 * vb);
+        double *be = al + (size_t)k * r;
+        Z *part = reinterpret_cast<Z *>(
+            (reinterpret_cast<uintptr_t>(be + (size_t)k * r) + 255) & ~uintptr_t(255));
+        copy_block(reinterpret_cast<const Z *>(dV0), ldv0, w, r, N, r, s);
+        lanczos_update(v, vp, w, r, N, r, al, be, 0, 1, s);
+        for (int j = 0; j < k; ++j) {
+            filter_gemm(reinterpret_cast<const Z *>(dH), ldh, N, v, r, nullptr, r,
+                        w, r, r, 1.0, 0.0, 0.0, part, s);
+            lanczos_update(v, vp, w, r, N, r, al, be, j, 0, s);
+        }
+        CHASE_HIP(hipMemcpyAsync(h_alpha, al, sizeof(double) * k * r,
+                                 hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipMemcpyAsync(h_beta, be, sizeof(double) * k * r,
+                                 hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_lanczos_bounds(const double *h_alpha, const double *h_beta,
+                         int32_t k, int32_t r, int64_t N, int32_t ne,
+                         double *out4) {
+    return guarded([&]() -> int {
+        REQUIRE(h_alpha && h_beta && out4 && k >= 1 && r >= 1 && N >= 1 && ne >= 1,
+                "bad arguments");
+        const Bounds b = lanczos_bounds(h_alpha, h_beta, k, r, N, ne);
+        out4[0] = b.mu1;
+        out4[1] = b.mu_ne;
+        out4[2] = b.bsup;
+        out4[3] = b.hnorm;
+        return CHASE_OK;
+    });
+}
+
+int chase_qr(chase_z *dV, int64_t N, int64_t ldv, int32_t n, int32_t nlocked,
+             void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "bad N");
+        REQUIRE(n >= 1 && n <= 1024 && n <= N && ldv >= n, "bad n/ldv");
+        REQUIRE(nlocked >= 0 && nlocked <= n, "bad nlocked");
+        REQUIRE(dV, "NULL pointer");
+        const int na = n - nlocked;
+        if (na == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        size_t gp = gram_partial_elems(N, na, na);
+        if (nlocked > 0) gp = std::max(gp, gram_partial_elems(N, nlocked, na));
+        const size_t nn = (size_t)n * n;
+        const size_t blk = (size_t)N * n * sizeof(Z);
+        DevBuf buf(2 * blk + (gp + 3 * nn + n + 8) * sizeof(Z) + 1024, s);
+        Z *Vc = buf.as<Z>();
+        Z *B1 = buf.as<Z>(blk);
+        Z *gpart = buf.as<Z>(2 * blk);
+        Z *G = gpart + gp;
+        Z *Bq = G + nn;
+        Z *cw = Bq + nn;
+        int *dinfo = reinterpret_cast<int *>(cw + nn + n / 2 + 2);
+        copy_block(reinterpret_cast<Z *>(dV), ldv, Vc, n, N, n, s);
+        qr_block(Vc, B1, n, N, nlocked, n, G, Bq, cw, gpart, dinfo, s);
+        int hinfo[3] = {0, 0, 0};
+        CHASE_HIP(hipMemcpyAsync(hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+        copy_block(Vc, n, reinterpret_cast<Z *>(dV), ldv, N, n, s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < 3; ++i)
+            if (hinfo[i])
+                throw Error(CHASE_EINTERNAL, "QR: CholeskyQR breakdown at column " +
+                                                 std::to_string(hinfo[i] - 1));
+        return CHASE_OK;
+    });
+}
+
+int chase_rayleigh_ritz(const chase_z *dH, int64_t N, int64_t ldh,
+                        chase_z *dQ, int64_t ldq, int32_t n, double *h_theta,
+                        double *h_resid, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31 && ldh >= N, "bad N/ldh");
+        REQUIRE(n >= 1 && n <= 1024 && n <= N && ldq >= n, "bad n/ldq");
+        REQUIRE(dH && dQ && h_theta, "NULL pointer");
+        hipStream_t s = S(stream);
+        const size_t blk = (size_t)N * n * sizeof(Z);
+        const size_t nn = (size_t)n * n;
+        size_t fp = filter_partial_elems(N, n);
+        size_t gp = gram_partial_elems(N, n, n);
+        const size_t np = norm_partial_elems(N, n);
+        DevBuf buf(4 * blk + (fp + gp + 2 * nn + jacobi_work_elems(n)) * sizeof(Z) +
+                       (np + 2 * (size_t)n) * sizeof(double) + 4096, s);
+        char *b = buf.as<char>();
+        auto take = [&](size_t bytes) {
+            char *at = b;
+            b += (bytes + 255) & ~size_t(255);
+            return at;
+        };
+        Z *Qc = reinterpret_cast<Z *>(take(blk));
+        Z *W = reinterpret_cast<Z *>(take(blk));
+        Z *T = reinterpret_cast<Z *>(take(blk));
+        Z *B1 = reinterpret_cast<Z *>(take(blk));
+        Z *fpart = reinterpret_cast<Z *>(take(fp * sizeof(Z)));
+        Z *gpart = reinterpret_cast<Z *>(take(gp * sizeof(Z)));
+        Z *G = reinterpret_cast<Z *>(take(nn * sizeof(Z)));
+        Z *Y = reinterpret_cast<Z *>(take(nn * sizeof(Z)));
+        Z *jw = reinterpret_cast<Z *>(take(jacobi_work_elems(n) * sizeof(Z)));
+        double *th = reinterpret_cast<double *>(take(n * sizeof(double)));
+        double *rs = reinterpret_cast<double *>(take(n * sizeof(double)));
+        double *np_ = reinterpret_cast<double *>(take(np * sizeof(double)));
+        double hw[4];
+        copy_block(reinterpret_cast<Z *>(dQ), ldq, Qc, n, N, n, s);
+        rr_block(reinterpret_cast<const Z *>(dH), ldh, N, Qc, W, T, B1, n, n, G,
+                 Y, jw, th, h_resid ? rs : nullptr, fpart, gpart, np_, hw, s);
+        copy_block(Qc, n, reinterpret_cast<Z *>(dQ), ldq, N, n, s);
+        CHASE_HIP(hipMemcpyAsync(h_theta, th, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        if (h_resid)
+            CHASE_HIP(hipMemcpyAsync(h_resid, rs, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_residuals(const chase_z *dH, int64_t N, int64_t ldh,
+                    const chase_z *dV, int64_t ldv, int32_t n,
+                    const double *h_theta, double *h_resid, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31 && ldh >= N, "bad N/ldh");
+        REQUIRE(n >= 1 && ldv >= n, "bad n/ldv");
+        REQUIRE(dH && dV && h_theta && h_resid, "NULL pointer");
+        hipStream_t s = S(stream);
+        const size_t blk = (size_t)N * n * sizeof(Z);
+        const size_t fp = filter_partial_elems(N, n);
+        const size_t np = norm_partial_elems(N, n);
+        DevBuf buf(blk + fp * sizeof(Z) + (np + n) * sizeof(double) + 1024, s);
+        Z *T = buf.as<Z>();
+        Z *part = buf.as<Z>((blk + 255) & ~size_t(255));
+        double *th = reinterpret_cast<double *>(part + fp);
+        double *np_ = th + n;
+        CHASE_HIP(hipMemcpyAsync(th, h_theta, sizeof(double) * n, hipMemcpyHostToDevice, s));
+        // T = H V - diag(theta) applied through the epilogue is not possible
+        // per column, so form H V and subtract in the norm kernel.
+        filter_gemm(reinterpret_cast<const Z *>(dH), ldh, N,
+                    reinterpret_cast<const Z *>(dV), ldv, nullptr, n, T, n, n, 1.0,
+                    0.0, 0.0, part, s);
+        col_norms(T, n, reinterpret_cast<const Z *>(dV), ldv, th, N, n, np_, th, s);
+        CHASE_HIP(hipMemcpyAsync(h_resid, th, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
+                void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(n >= 1 && n <= 1024, "n must be in [1, 1024]");
+        REQUIRE(dG && h_w && dY, "NULL pointer");
+        hipStream_t s = S(stream);
+        const size_t nn = (size_t)n * n;
+        DevBuf buf((nn + jacobi_work_elems(n)) * sizeof(Z) + n * sizeof(double) + 512, s);
+        Z *A = buf.as<Z>();
+        Z *jw = A + nn;
+        double *w = reinterpret_cast<double *>(jw + jacobi_work_elems(n));
+        double hw[4];
+        CHASE_HIP(hipMemcpyAsync(A, dG, nn * sizeof(Z), hipMemcpyDeviceToDevice, s));
+        jacobi_eig(A, n, w, reinterpret_cast<Z *>(dY), jw, hw, s);
+        CHASE_HIP(hipMemcpyAsync(h_w, w, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
+                  double tol_abs, double alpha, double beta, int32_t degree_max,
+                  int32_t extra, int32_t *h_degrees) {
+    return guarded([&]() -> int {
+        REQUIRE(n >= 0 && (n == 0 || (h_theta && h_resid && h_degrees)), "bad arguments");
+        REQUIRE(beta > alpha, "need alpha < beta");
+        REQUIRE(tol_abs > 0.0 && degree_max >= 2 && extra >= 0, "bad tol/degree");
+        const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+        for (int j = 0; j < n; ++j)
+            h_degrees[j] = degree_for(h_resid[j], tol_abs, h_theta[j], c, e, degree_max, extra);
+        return CHASE_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations shared by the HIP sources of libchase_mi355x.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace chase {
+
+using Z = double2;   // complex128: .x = real, .y = imaginary
+
+// Error carried up to the C ABI, which turns it into a status code.
+struct Error : std::runtime_error {
+    int status;
+    Error(int st, const std::string &m) : std::runtime_error(m), status(st) {}
+};
+
+#define CHASE_HIP(call)                                                       \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            throw ::chase::Error(3, std::string(#call) + ": " +              \
+                                        hipGetErrorString(e_));               \
+    } while (0)
+
+inline void check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        throw Error(3, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- kernels
+// All vector blocks are row-major (element (i, j) at p[i*ld + j]); H is
+// column-major.  Every launcher enqueues on `s` and returns immediately.
+
+// Filter GEMM: W[:, 0:n] = a*H*Y + b*Y + g*X (X may be null when g == 0;
+// W may alias X).  `part` is scratch for split-K partial sums of
+// filter_partial_elems(N, n) elements (may be null if that is 0).
+struct FilterPlan {
+    int wn;       // 16-column blocks per wave (1..10)
+    int cb;       // column blocks of 16*wn columns
+    int rb;       // row blocks of 64 rows
+    int splits;   // K splits (1 = epilogue fused)
+    int kchunk;   // K rows per split (multiple of 4)
+};
+FilterPlan filter_plan(int64_t N, int n);
+size_t filter_partial_elems(int64_t N, int n);
+void filter_gemm(const Z *H, int64_t ldh, int64_t N, const Z *Y, int64_t ldy,
+                 const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
+                 double b, double g, Z *part, hipStream_t s,
+                 hipEvent_t after_mfma = nullptr);
+
+// C (p x q, row-major ldc) = A^H B over N rows; A: N x p, B: N x q.
+// `part` holds gram_partial_elems(N, p, q) elements of split-K partials.
+size_t gram_partial_elems(int64_t N, int p, int q);
+void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N, int p,
+          int q, Z *C, int64_t ldc, Z *part, hipStream_t s);
+
+// C (N x q) = alpha * A (N x p) * B (p x q, row-major ldb) + beta * C0.
+// C0 may alias C or be null (beta == 0).  C must not overlap A.
+void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N, int p,
+          int q, double alpha, const Z *C0, int64_t ldc0, double beta, Z *C,
+          int64_t ldc, hipStream_t s);
+
+// Column norms of (V - V2 * diag(theta)) or of V (V2 == null); deterministic
+// two-pass reduction.  out: n doubles on the device.  part: norm_partial_elems.
+size_t norm_partial_elems(int64_t N, int n);
+void col_norms(const Z *V, int64_t ldv, const Z *V2, int64_t ldv2,
+               const double *theta, int64_t N, int n, double *part,
+               double *out, hipStream_t s);
+
+// Row-major block copies and layout changes.
+void copy_block(const Z *src, int64_t lds, Z *dst, int64_t ldd, int64_t N,
+                int n, hipStream_t s);
+// dst[i*ldd + j] = src[i*lds + perm[j]]  (perm on the device)
+void permute_cols(const Z *src, int64_t lds, Z *dst, int64_t ldd, int64_t N,
+                  int n, const int *perm, hipStream_t s);
+// Column-major (ldc) <-> row-major (ldr), N x n.
+void colmajor_to_rowmajor(const Z *src, int64_t ldc, Z *dst, int64_t ldr,
+                          int64_t N, int n, hipStream_t s);
+void rowmajor_to_colmajor(const Z *src, int64_t ldr, Z *dst, int64_t ldc,
+                          int64_t N, int n, hipStream_t s);
+// Phase normalisation (largest-modulus entry real positive) of each column
+// of a row-major block, written column-major to dst.  scratch: 2*n*nblk.
+size_t phase_scratch_elems(int64_t N, int n);
+void phase_normalise_out(const Z *V, int64_t ldv, int64_t N, int n, Z *dst,
+                         int64_t ldd, double *scratch, hipStream_t s);
+
+// Complex Gaussian block (E|z|^2 = 1) from Philox4x32-10 keyed by seed,
+// counter (i, j, stream, 0); row-major ld.
+void random_block(Z *V, int64_t ld, int64_t N, int n, uint64_t seed,
+                  uint32_t stream, hipStream_t s);
+
+// Non-finite check of the column-major H: *flag (device int) set to 1 if any
+// entry is NaN/Inf.  The caller zeroes the flag.
+void check_finite(const Z *H, int64_t ldh, int64_t N, int *flag, hipStream_t s);
+
+// Lanczos: one fused update per run after w = H v (r runs are columns of
+// row-major N x r blocks):  alpha = Re v^H w;  w -= alpha v + beta_prev vp;
+// beta = ||w||;  vp <- v;  v <- w / beta.  Writes alpha/beta for `step`.
+// If `normalise_only`, just sets v <- v0 / ||v0|| and vp <- 0.
+void lanczos_update(Z *v, Z *vp, Z *w, int64_t ld, int64_t N, int r,
+                    double *alpha, double *beta, int step, int normalise_only,
+                    hipStream_t s);
+
+// ------------------------------------------------- small dense (n <= 512)
+// G (n x n Hermitian, row-major ld n) -> in place lower Cholesky factor of
+// D G D + shift I with D = diag(1/sqrt(G_jj)); then writes
+// B = D * L^{-H} (row-major n x n, the right factor for V <- V B).
+// info: device int, set to 1 + column on a non-positive pivot, else 0.
+void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
+                    hipStream_t s);
+// Reduced Hermitian eigenproblem by cyclic Jacobi.  A: n x n row-major
+// (overwritten).  On return w (device, ascending) and Y (row-major, columns
+// are eigenvectors).  work: jacobi_work_elems(n) complex elements.
+size_t jacobi_work_elems(int n);
+void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
+                hipStream_t s);
+// Symmetrise: G <- (G + G^H)/2, real diagonal.
+void hermitise(Z *G, int n, hipStream_t s);
+
+}  // namespace chase

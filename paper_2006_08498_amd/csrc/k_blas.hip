@@ -1,0 +1,626 @@
+// Tall-skinny products, reductions and layout kernels used by the QR, RR,
+// Resid and Lanczos phases.  Blocks are row-major N x n (element (i, j) at
+// p[i*ld + j]); every reduction has a fixed order (no atomics), so results
+// are bitwise reproducible.
+#include "common.h"
+
+#include <algorithm>
+
+namespace chase {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ gram
+// part[s] (p x q) = sum over rows of chunk s of conj(A[i, :])^T B[i, :].
+// Workgroup = 4 waves over interleaved 4-row steps of the chunk, one
+// 16 x 16*WN tile of C; the four wave sums are added in LDS in wave order.
+template <int WN>
+__global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
+                                              int64_t lda,
+                                              const Z *__restrict__ B,
+                                              int64_t ldb, int N, int p, int q,
+                                              int pb, int qb, int chunk,
+                                              Z *__restrict__ part) {
+    __shared__ double red[3][64 * 8 * WN];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, qq = lane >> 4;
+    int t = blockIdx.x;
+    const int ib = t % pb;
+    t /= pb;
+    const int jb = t % qb;
+    const int s = t / qb;
+    const int p0 = ib * 16, q0 = jb * 16 * WN;
+    const int kbeg = s * chunk, kend = min(N, kbeg + chunk);
+    const int acol = min(p0 + r, p - 1);
+    int bcol[WN];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) bcol[c] = min(q0 + 16 * c + r, q - 1);
+    v4d cr[WN], ci[WN];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) {
+        cr[c] = v4d{0, 0, 0, 0};
+        ci[c] = v4d{0, 0, 0, 0};
+    }
+    for (int k = kbeg + 4 * wave; k < kend; k += 16) {
+        const int row = k + qq;
+        const bool ok = row < kend;
+        const int rr = ok ? row : kbeg;
+        Z a = A[(int64_t)rr * lda + acol];
+        if (!ok) a = Z{0.0, 0.0};
+        const double nay = -a.y;
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+            const Z bv = B[(int64_t)rr * ldb + bcol[c]];
+            cr[c] = mfma64(a.x, bv.x, cr[c]);
+            ci[c] = mfma64(a.x, bv.y, ci[c]);
+            cr[c] = mfma64(a.y, bv.y, cr[c]);
+            ci[c] = mfma64(nay, bv.x, ci[c]);
+        }
+    }
+    // Fixed-order sum of the four waves' tiles.
+    if (wave > 0) {
+#pragma unroll
+        for (int c = 0; c < WN; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                red[wave - 1][(c * 8 + v) * 64 + lane] = cr[c][v];
+                red[wave - 1][(c * 8 + 4 + v) * 64 + lane] = ci[c][v];
+            }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int c = 0; c < WN; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    cr[c][v] += red[w][(c * 8 + v) * 64 + lane];
+                    ci[c][v] += red[w][(c * 8 + 4 + v) * 64 + lane];
+                }
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+            const int col = q0 + 16 * c + r;
+            if (col >= q) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = p0 + qq + 4 * v;   // FP64 MFMA: register v holds row qq + 4v
+                if (row >= p) continue;
+                part[((int64_t)s * p + row) * q + col] = Z{cr[c][v], ci[c][v]};
+            }
+        }
+    }
+}
+
+__global__ void k_sum_parts(const Z *__restrict__ part, int nparts, int p,
+                            int q, Z *__restrict__ C, int64_t ldc) {
+    const int64_t total = (int64_t)p * q;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int s = 0; s < nparts; ++s) {
+            const Z v = part[(int64_t)s * total + t];
+            sr += v.x;
+            si += v.y;
+        }
+        const int64_t i = t / q, j = t - i * q;
+        C[i * ldc + j] = Z{sr, si};
+    }
+}
+
+struct GramPlan {
+    int wn, pb, qb, chunks, chunk;
+};
+
+GramPlan gram_plan(int64_t N, int p, int q) {
+    GramPlan g{};
+    const int nb = (q + 15) / 16;
+    g.qb = (nb + 3) / 4;   // at most 4 tiles per wave (LDS: 48 KiB)
+    g.wn = (nb + g.qb - 1) / g.qb;
+    g.pb = (p + 15) / 16;
+    const int64_t tiles = (int64_t)g.pb * g.qb;
+    int64_t want = (1024 + tiles - 1) / tiles;
+    int64_t maxc = (N + 255) / 256;
+    g.chunks = (int)std::max<int64_t>(1, std::min(want, maxc));
+    int64_t ch = (N + g.chunks - 1) / g.chunks;
+    ch = (ch + 15) & ~int64_t(15);
+    g.chunk = (int)ch;
+    g.chunks = (int)((N + ch - 1) / ch);
+    return g;
+}
+
+template <int WN>
+void launch_gram(const GramPlan &g, const Z *A, int64_t lda, const Z *B,
+                 int64_t ldb, int N, int p, int q, Z *part, hipStream_t s) {
+    const int blocks = g.pb * g.qb * g.chunks;
+    hipLaunchKernelGGL(k_gram<WN>, dim3(blocks), dim3(256), 0, s, A, lda, B,
+                       ldb, N, p, q, g.pb, g.qb, g.chunk, part);
+}
+
+// ------------------------------------------------------------------ tsmm
+// C (N x q) = alpha * A (N x p) B (p x q) + beta * C0; wave = 16 rows x
+// 16*WN columns, K = p.
+template <int WN>
+__global__ __launch_bounds__(256) void k_tsmm(
+    const Z *__restrict__ A, int64_t lda, const Z *__restrict__ B, int64_t ldb,
+    int N, int p, int q, double alpha, const Z *C0, int64_t ldc0, double beta,
+    Z *C, int64_t ldc, int cb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, qq = lane >> 4;
+    const int rbk = blockIdx.x / cb, cbk = blockIdx.x % cb;
+    const int row0 = rbk * 64 + wave * 16;
+    if (row0 >= N) return;
+    const int col0 = cbk * 16 * WN;
+    const int arow = min(row0 + r, N - 1);
+    const Z *ap = A + (int64_t)arow * lda;
+    int bcol[WN];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) bcol[c] = min(col0 + 16 * c + r, q - 1);
+    v4d cr[WN], ci[WN];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) {
+        cr[c] = v4d{0, 0, 0, 0};
+        ci[c] = v4d{0, 0, 0, 0};
+    }
+    for (int k = 0; k < p; k += 4) {
+        const int kk = k + qq;
+        const bool ok = kk < p;
+        const int kc = ok ? kk : 0;
+        Z a = ap[kc];
+        if (!ok) a = Z{0.0, 0.0};
+        const double nay = -a.y;
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+            const Z bv = B[(int64_t)kc * ldb + bcol[c]];
+            cr[c] = mfma64(a.x, bv.x, cr[c]);
+            ci[c] = mfma64(a.x, bv.y, ci[c]);
+            cr[c] = mfma64(nay, bv.y, cr[c]);
+            ci[c] = mfma64(a.y, bv.x, ci[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < WN; ++c) {
+        const int col = col0 + 16 * c + r;
+        if (col >= q) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + qq + 4 * v;   // FP64 MFMA: register v holds row qq + 4v
+            if (row >= N) continue;
+            Z o{alpha * cr[c][v], alpha * ci[c][v]};
+            if (beta != 0.0) {
+                const Z z = C0[(int64_t)row * ldc0 + col];
+                o.x += beta * z.x;
+                o.y += beta * z.y;
+            }
+            C[(int64_t)row * ldc + col] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------ col norms
+// part[blk][j] = sum_{i in blk} |V[i,j] - theta_j V2[i,j]|^2
+__global__ __launch_bounds__(256) void k_colnorm_part(
+    const Z *__restrict__ V, int64_t ldv, const Z *__restrict__ V2,
+    int64_t ldv2, const double *__restrict__ theta, int N, int n, int rows,
+    double *__restrict__ part) {
+    const int blk = blockIdx.x;
+    const int i0 = blk * rows, i1 = min(N, i0 + rows);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double acc = 0.0;
+        const double th = V2 ? theta[j] : 0.0;
+        for (int i = i0; i < i1; ++i) {
+            Z v = V[(int64_t)i * ldv + j];
+            if (V2) {
+                const Z u = V2[(int64_t)i * ldv2 + j];
+                v.x -= th * u.x;
+                v.y -= th * u.y;
+            }
+            acc += v.x * v.x + v.y * v.y;
+        }
+        part[(int64_t)blk * n + j] = acc;
+    }
+}
+
+__global__ void k_colnorm_final(const double *__restrict__ part, int nblk,
+                                int n, double *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * n + j];
+    out[j] = sqrt(acc);
+}
+
+int norm_blocks(int64_t N) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 63) / 64));
+}
+
+// ------------------------------------------------------------ layouts
+__global__ void k_copy(const Z *__restrict__ src, int64_t lds, Z *dst,
+                       int64_t ldd, int N, int n) {
+    const int64_t total = (int64_t)N * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        dst[i * ldd + j] = src[i * lds + j];
+    }
+}
+
+__global__ void k_permute(const Z *__restrict__ src, int64_t lds,
+                          Z *__restrict__ dst, int64_t ldd, int N, int n,
+                          const int *__restrict__ perm) {
+    const int64_t total = (int64_t)N * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        dst[i * ldd + j] = src[i * lds + perm[j]];
+    }
+}
+
+// 32 x 32 tiles through LDS so both sides are coalesced.
+__global__ __launch_bounds__(256) void k_c2r(const Z *__restrict__ src,
+                                             int64_t ldc, Z *__restrict__ dst,
+                                             int64_t ldr, int N, int n) {
+    __shared__ Z tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int i = i0 + tx, j = j0 + jj;
+        if (i < N && j < n) tile[jj][tx] = src[i + (int64_t)j * ldc];
+    }
+    __syncthreads();
+    for (int ii = ty; ii < 32; ii += 8) {
+        const int i = i0 + ii, j = j0 + tx;
+        if (i < N && j < n) dst[(int64_t)i * ldr + j] = tile[tx][ii];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_r2c(const Z *__restrict__ src,
+                                             int64_t ldr, Z *__restrict__ dst,
+                                             int64_t ldc, int N, int n,
+                                             const Z *__restrict__ phase) {
+    __shared__ Z tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int ii = ty; ii < 32; ii += 8) {
+        const int i = i0 + ii, j = j0 + tx;
+        if (i < N && j < n) tile[ii][tx] = src[(int64_t)i * ldr + j];
+    }
+    __syncthreads();
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int i = i0 + tx, j = j0 + jj;
+        if (i < N && j < n) {
+            Z v = tile[tx][jj];
+            if (phase) {
+                const Z ph = phase[j];   // (conj(v_max)/|v_max|, index)
+                const Z o{v.x * ph.x - v.y * ph.y, v.x * ph.y + v.y * ph.x};
+                v = o;
+                if ((double)i == phase[n + j].x) v.y = 0.0;
+            }
+            dst[i + (int64_t)j * ldc] = v;
+        }
+    }
+}
+
+// Largest |v_ij|^2 per column (lowest index on ties), two passes.
+__global__ __launch_bounds__(256) void k_absmax_part(
+    const Z *__restrict__ V, int64_t ldv, int N, int n, int rows,
+    double *__restrict__ part) {
+    const int blk = blockIdx.x;
+    const int i0 = blk * rows, i1 = min(N, i0 + rows);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double best = -1.0, bi = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const Z v = V[(int64_t)i * ldv + j];
+            const double m = v.x * v.x + v.y * v.y;
+            if (m > best) {
+                best = m;
+                bi = i;
+            }
+        }
+        part[((int64_t)blk * n + j) * 2] = best;
+        part[((int64_t)blk * n + j) * 2 + 1] = bi;
+    }
+}
+
+// phase[j] = conj(v_max)/|v_max|, phase[n + j].x = row of v_max.
+__global__ void k_absmax_final(const double *__restrict__ part, int nblk,
+                               const Z *__restrict__ V, int64_t ldv, int n,
+                               Z *__restrict__ phase) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double best = -1.0, bi = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double m = part[((int64_t)b * n + j) * 2];
+        if (m > best) {
+            best = m;
+            bi = part[((int64_t)b * n + j) * 2 + 1];
+        }
+    }
+    const Z v = V[(int64_t)bi * ldv + j];
+    const double a = sqrt(v.x * v.x + v.y * v.y);
+    phase[j] = a > 0.0 ? Z{v.x / a, -v.y / a} : Z{1.0, 0.0};
+    phase[n + j] = Z{bi, 0.0};
+}
+
+// ------------------------------------------------------------ random
+// Philox4x32-10 (Salmon et al., SC'11): round multipliers 0xD2511F53,
+// 0xCD9E8D57, key increments 0x9E3779B9, 0xBB67AE85.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0,
+                                         uint32_t k1) {
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) *
+           (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_random(Z *V, int64_t ld, int N, int n, uint32_t k0,
+                         uint32_t k1, uint32_t stream) {
+    const int64_t total = (int64_t)N * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)j, stream, 0u};
+        philox10(c, k0, k1);
+        const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        const double s = 0.70710678118654752440;
+        V[i * ld + j] = Z{rad * cs * s, rad * sn * s};
+    }
+}
+
+__global__ void k_check_finite(const Z *__restrict__ H, int64_t ldh, int N,
+                               int *flag) {
+    const int64_t total = (int64_t)N * N;
+    int bad = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / N, i = t - j * N;
+        const Z v = H[i + j * ldh];
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+    }
+    if (bad) *flag = 1;   // every writer stores the same value
+}
+
+// ------------------------------------------------------------ Lanczos
+// One workgroup per run (column `run` of the row-major N x r blocks).
+template <int NT>
+__device__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double out = sh[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(1024) void k_lanczos(Z *v, Z *vp, Z *w,
+                                                  int64_t ld, int N, int r,
+                                                  double *alpha, double *beta,
+                                                  int step, int normalise_only) {
+    __shared__ double sh[1024];
+    const int run = blockIdx.x;
+    const int t = threadIdx.x;
+    if (normalise_only) {
+        double s = 0.0;
+        for (int i = t; i < N; i += 1024) {
+            const Z x = w[(int64_t)i * ld + run];
+            s += x.x * x.x + x.y * x.y;
+        }
+        const double nrm = sqrt(block_sum<1024>(s, sh));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int i = t; i < N; i += 1024) {
+            const Z x = w[(int64_t)i * ld + run];
+            v[(int64_t)i * ld + run] = Z{x.x * inv, x.y * inv};
+            vp[(int64_t)i * ld + run] = Z{0.0, 0.0};
+        }
+        return;
+    }
+    double s = 0.0;
+    for (int i = t; i < N; i += 1024) {
+        const Z a = v[(int64_t)i * ld + run], b = w[(int64_t)i * ld + run];
+        s += a.x * b.x + a.y * b.y;     // Re(conj(v) w)
+    }
+    const double al = block_sum<1024>(s, sh);
+    const double bp = step > 0 ? beta[(step - 1) * r + run] : 0.0;
+    s = 0.0;
+    for (int i = t; i < N; i += 1024) {
+        const int64_t o = (int64_t)i * ld + run;
+        const Z a = v[o], c = vp[o];
+        Z b = w[o];
+        b.x -= al * a.x + bp * c.x;
+        b.y -= al * a.y + bp * c.y;
+        w[o] = b;
+        s += b.x * b.x + b.y * b.y;
+    }
+    const double be = sqrt(block_sum<1024>(s, sh));
+    const double inv = be > 0.0 ? 1.0 / be : 0.0;
+    for (int i = t; i < N; i += 1024) {
+        const int64_t o = (int64_t)i * ld + run;
+        const Z a = v[o], b = w[o];
+        vp[o] = a;
+        v[o] = Z{b.x * inv, b.y * inv};
+    }
+    if (t == 0) {
+        alpha[step * r + run] = al;
+        beta[step * r + run] = be;
+    }
+}
+
+inline int grid_for(int64_t total) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+}
+
+}  // namespace
+
+size_t gram_partial_elems(int64_t N, int p, int q) {
+    const GramPlan g = gram_plan(N, p, q);
+    return (size_t)g.chunks * (size_t)p * (size_t)q;
+}
+
+void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
+          int q, Z *C, int64_t ldc, Z *part, hipStream_t s) {
+    if (p <= 0 || q <= 0) return;
+    const int N = (int)N64;
+    const GramPlan g = gram_plan(N64, p, q);
+    switch (g.wn) {
+#define CASE(w) case w: launch_gram<w>(g, A, lda, B, ldb, N, p, q, part, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4)
+#undef CASE
+        default: throw Error(7, "gram: bad tile width");
+    }
+    check_launch("k_gram");
+    hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((int64_t)p * q)), dim3(256),
+                       0, s, part, g.chunks, p, q, C, ldc);
+    check_launch("k_sum_parts");
+}
+
+void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
+          int q, double alpha, const Z *C0, int64_t ldc0, double beta, Z *C,
+          int64_t ldc, hipStream_t s) {
+    if (N64 <= 0 || q <= 0) return;
+    const int N = (int)N64;
+    const int nb = (q + 15) / 16;
+    const int cb = (nb + 7) / 8;
+    const int wn = (nb + cb - 1) / cb;
+    const int rb = (N + 63) / 64;
+    const dim3 grid(rb * cb);
+    switch (wn) {
+#define CASE(w)                                                                \
+    case w:                                                                    \
+        hipLaunchKernelGGL(k_tsmm<w>, grid, dim3(256), 0, s, A, lda, B, ldb, N, \
+                           p, q, alpha, C0, ldc0, beta, C, ldc, cb);           \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error(7, "tsmm: bad tile width");
+    }
+    check_launch("k_tsmm");
+}
+
+size_t norm_partial_elems(int64_t N, int n) {
+    return (size_t)norm_blocks(N) * (size_t)n * 2;
+}
+
+void col_norms(const Z *V, int64_t ldv, const Z *V2, int64_t ldv2,
+               const double *theta, int64_t N, int n, double *part,
+               double *out, hipStream_t s) {
+    if (n <= 0) return;
+    const int nblk = norm_blocks(N);
+    const int rows = (int)((N + nblk - 1) / nblk);
+    hipLaunchKernelGGL(k_colnorm_part, dim3(nblk), dim3(256), 0, s, V, ldv, V2,
+                       ldv2, theta, (int)N, n, rows, part);
+    check_launch("k_colnorm_part");
+    hipLaunchKernelGGL(k_colnorm_final, dim3((n + 255) / 256), dim3(256), 0, s,
+                       part, nblk, n, out);
+    check_launch("k_colnorm_final");
+}
+
+void copy_block(const Z *src, int64_t lds, Z *dst, int64_t ldd, int64_t N,
+                int n, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(N * n)), dim3(256), 0, s, src, lds,
+                       dst, ldd, (int)N, n);
+    check_launch("k_copy");
+}
+
+void permute_cols(const Z *src, int64_t lds, Z *dst, int64_t ldd, int64_t N,
+                  int n, const int *perm, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_permute, dim3(grid_for(N * n)), dim3(256), 0, s, src,
+                       lds, dst, ldd, (int)N, n, perm);
+    check_launch("k_permute");
+}
+
+void colmajor_to_rowmajor(const Z *src, int64_t ldc, Z *dst, int64_t ldr,
+                          int64_t N, int n, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((n + 31) / 32));
+    hipLaunchKernelGGL(k_c2r, grid, dim3(256), 0, s, src, ldc, dst, ldr, (int)N,
+                       n);
+    check_launch("k_c2r");
+}
+
+void rowmajor_to_colmajor(const Z *src, int64_t ldr, Z *dst, int64_t ldc,
+                          int64_t N, int n, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((n + 31) / 32));
+    hipLaunchKernelGGL(k_r2c, grid, dim3(256), 0, s, src, ldr, dst, ldc, (int)N,
+                       n, (const Z *)nullptr);
+    check_launch("k_r2c");
+}
+
+size_t phase_scratch_elems(int64_t N, int n) {
+    // absmax partials (2 doubles per block and column) + 2n complex phases
+    return (size_t)norm_blocks(N) * (size_t)n * 2 + (size_t)n * 4;
+}
+
+void phase_normalise_out(const Z *V, int64_t ldv, int64_t N, int n, Z *dst,
+                         int64_t ldd, double *scratch, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    const int nblk = norm_blocks(N);
+    const int rows = (int)((N + nblk - 1) / nblk);
+    double *part = scratch;
+    Z *phase = reinterpret_cast<Z *>(scratch + (size_t)nblk * n * 2);
+    hipLaunchKernelGGL(k_absmax_part, dim3(nblk), dim3(256), 0, s, V, ldv,
+                       (int)N, n, rows, part);
+    check_launch("k_absmax_part");
+    hipLaunchKernelGGL(k_absmax_final, dim3((n + 255) / 256), dim3(256), 0, s,
+                       part, nblk, V, ldv, n, phase);
+    check_launch("k_absmax_final");
+    const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((n + 31) / 32));
+    hipLaunchKernelGGL(k_r2c, grid, dim3(256), 0, s, V, ldv, dst, ldd, (int)N,
+                       n, (const Z *)phase);
+    check_launch("k_r2c");
+}
+
+void random_block(Z *V, int64_t ld, int64_t N, int n, uint64_t seed,
+                  uint32_t stream, hipStream_t s) {
+    if (N <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_random, dim3(grid_for(N * n)), dim3(256), 0, s, V, ld,
+                       (int)N, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                       stream);
+    check_launch("k_random");
+}
+
+void check_finite(const Z *H, int64_t ldh, int64_t N, int *flag,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(N * N)), dim3(256), 0, s,
+                       H, ldh, (int)N, flag);
+    check_launch("k_check_finite");
+}
+
+void lanczos_update(Z *v, Z *vp, Z *w, int64_t ld, int64_t N, int r,
+                    double *alpha, double *beta, int step, int normalise_only,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos, dim3(r), dim3(1024), 0, s, v, vp, w, ld,
+                       (int)N, r, alpha, beta, step, normalise_only);
+    check_launch("k_lanczos");
+}
+
+}  // namespace chase

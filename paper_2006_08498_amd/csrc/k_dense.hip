@@ -1,0 +1,354 @@
+// Small dense kernels on the reduced matrices (order n <= 1024, typically
+// nev + nex <= 400), all on the device so the solver never round-trips a
+// matrix through the host:
+//  * the CholeskyQR factor (QR phase): D = diag(G)^{-1/2}, Cholesky of
+//    D G D + shift I, and B = D L^{-H} so that V <- V B orthonormalises;
+//  * cyclic two-sided Jacobi for the reduced Hermitian eigenproblem of the
+//    Rayleigh-Ritz phase (round-robin pairing, one launch per round, every
+//    2 x 2 block updated independently: A' = J_a^H A J_b);
+//  * ordering of the eigenpairs, Hermitian symmetrisation.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace chase {
+namespace {
+
+__device__ __forceinline__ Z zmul(Z a, Z b) {
+    return Z{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ Z zconj(Z a) { return Z{a.x, -a.y}; }
+__device__ __forceinline__ Z zadd(Z a, Z b) { return Z{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Z zsub(Z a, Z b) { return Z{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------- CholeskyQR
+// One workgroup.  G (n x n row-major) -> lower Cholesky factor of
+// D G D + shift I in place; B = D L^{-H}; Linv in `work`.
+__global__ __launch_bounds__(1024) void k_chol_factor(Z *G, int n, double shift,
+                                                      Z *B, Z *work,
+                                                      int *info) {
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    double *dsc = reinterpret_cast<double *>(work);          // n doubles
+    Z *Linv = work + (n + 1) / 2 + 1;                        // n x n
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int j = t; j < n; j += nt) {
+        const double gjj = G[(int64_t)j * n + j].x;
+        if (!(gjj > 0.0) || !isfinite(gjj)) bad = j + 1;
+        dsc[j] = gjj > 0.0 ? 1.0 / sqrt(gjj) : 0.0;
+    }
+    __syncthreads();
+    if (bad) {
+        if (t == 0) *info = bad;
+        return;
+    }
+    // Scale and shift (lower triangle only is used below).
+    for (int64_t e = t; e < (int64_t)n * n; e += nt) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j > i) continue;
+        Z v = zscale(G[e], dsc[i] * dsc[j]);
+        if (i == j) v = Z{v.x + shift, 0.0};
+        G[e] = v;
+    }
+    __syncthreads();
+    // Right-looking Cholesky, lower.
+    for (int k = 0; k < n; ++k) {
+        const double piv = G[(int64_t)k * n + k].x;
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (t == 0) *info = k + 1;
+            return;   // uniform: every thread read the same pivot
+        }
+        const double l = sqrt(piv), il = 1.0 / l;
+        __syncthreads();
+        for (int i = k + 1 + t; i < n; i += nt)
+            G[(int64_t)i * n + k] = zscale(G[(int64_t)i * n + k], il);
+        __syncthreads();
+        if (t == 0) G[(int64_t)k * n + k] = Z{l, 0.0};
+        const int m = n - k - 1;
+        const int64_t cnt = (int64_t)m * (m + 1) / 2;
+        for (int64_t e = t; e < cnt; e += nt) {
+            // e -> (ii, jj) with jj <= ii in the trailing block
+            int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            while ((int64_t)ii * (ii + 1) / 2 > e) --ii;
+            while ((int64_t)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+            const int jj = (int)(e - (int64_t)ii * (ii + 1) / 2);
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            const Z lik = G[(int64_t)i * n + k], ljk = G[(int64_t)j * n + k];
+            G[(int64_t)i * n + j] = zsub(G[(int64_t)i * n + j], zmul(lik, zconj(ljk)));
+        }
+        __syncthreads();
+    }
+    // Columns of L^{-1} by forward substitution, one thread per column;
+    // thread j also writes row j of B = D L^{-H}.
+    for (int j = t; j < n; j += nt) {
+        const Z ljj = G[(int64_t)j * n + j];
+        Linv[(int64_t)j * n + j] = Z{1.0 / ljj.x, 0.0};
+        for (int i = j + 1; i < n; ++i) {
+            Z s{0.0, 0.0};
+            for (int k = j; k < i; ++k)
+                s = zadd(s, zmul(G[(int64_t)i * n + k], Linv[(int64_t)k * n + j]));
+            Linv[(int64_t)i * n + j] = zscale(s, -1.0 / G[(int64_t)i * n + i].x);
+        }
+        for (int i = 0; i < n; ++i) {
+            // B[j][i] = d_j * conj(Linv[i][j]) (zero below the diagonal)
+            B[(int64_t)j * n + i] =
+                i >= j ? zscale(zconj(Linv[(int64_t)i * n + j]), dsc[j]) : Z{0.0, 0.0};
+        }
+    }
+    if (t == 0) *info = 0;
+}
+
+// ---------------------------------------------------------- Jacobi
+// Round-robin pairing of m (even) indices, round r, pair k.
+__device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
+    int a, b;
+    if (k == 0) {
+        a = m - 1;
+        b = r;
+    } else {
+        a = (r + k) % (m - 1);
+        b = (r - k + (m - 1)) % (m - 1);
+    }
+    p = min(a, b);
+    q = max(a, b);
+}
+
+// J = [[c, s], [-s e, c e]] with e = conj(a_pq)/|a_pq| diagonalises the
+// 2 x 2 Hermitian [[a_pp, a_pq], [conj(a_pq), a_qq]] (complex phase then
+// real symmetric Jacobi rotation, Golub & Van Loan Alg. 8.5.1).
+struct Rot {
+    double c, s;
+    Z e;
+    double dp, dq;   // resulting diagonal
+    bool active;
+};
+
+__device__ Rot make_rot(const Z *A, int n, int p, int q) {
+    Rot R{1.0, 0.0, Z{1.0, 0.0}, 0.0, 0.0, false};
+    const double app = A[(int64_t)p * n + p].x;   // p < n always
+    R.dp = app;
+    if (q >= n) return R;      // phantom partner (n odd): identity
+    const double aqq = A[(int64_t)q * n + q].x;
+    const Z apq = A[(int64_t)p * n + q];
+    const double x = sqrt(apq.x * apq.x + apq.y * apq.y);
+    R.dp = app;
+    R.dq = aqq;
+    if (!(x > 1e-300) || x <= 1e-18 * (fabs(app) + fabs(aqq))) return R;
+    R.e = Z{apq.x / x, -apq.y / x};
+    const double tau = (aqq - app) / (2.0 * x);
+    double t;
+    if (fabs(tau) > 1e150) t = 0.5 / tau;
+    else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    R.c = 1.0 / sqrt(1.0 + t * t);
+    R.s = t * R.c;
+    R.dp = app - t * x;
+    R.dq = aqq + t * x;
+    R.active = true;
+    return R;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_round(
+    const Z *__restrict__ A, Z *__restrict__ A2, const Z *__restrict__ V,
+    Z *__restrict__ V2, int n, int m, int round) {
+    const int h = m / 2;
+    const int64_t nblk = (int64_t)h * h;
+    const int64_t total = nblk + (int64_t)n * h;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nblk) {
+            const int ka = (int)(t / h), kb = (int)(t - (int64_t)ka * h);
+            int pa, qa, pb, qb;
+            rr_pair(m, round, ka, pa, qa);
+            rr_pair(m, round, kb, pb, qb);
+            const Rot Ra = make_rot(A, n, pa, qa);
+            const Rot Rb = make_rot(A, n, pb, qb);
+            const bool qa_ok = qa < n, qb_ok = qb < n;
+            if (ka == kb) {
+                // Diagonal block: the rotation diagonalises it exactly.
+                A2[(int64_t)pa * n + pa] = Z{Ra.dp, 0.0};
+                if (qa_ok) {
+                    A2[(int64_t)qa * n + qa] = Z{Ra.dq, 0.0};
+                    A2[(int64_t)pa * n + qa] = Ra.active ? Z{0.0, 0.0} : A[(int64_t)pa * n + qa];
+                    A2[(int64_t)qa * n + pa] = Ra.active ? Z{0.0, 0.0} : A[(int64_t)qa * n + pa];
+                }
+                continue;
+            }
+            const Z zero{0.0, 0.0};
+            const Z m00 = A[(int64_t)pa * n + pb];
+            const Z m01 = qb_ok ? A[(int64_t)pa * n + qb] : zero;
+            const Z m10 = qa_ok ? A[(int64_t)qa * n + pb] : zero;
+            const Z m11 = (qa_ok && qb_ok) ? A[(int64_t)qa * n + qb] : zero;
+            // T = M J_b
+            const Z j00b{Rb.c, 0.0}, j01b{Rb.s, 0.0};
+            const Z j10b = zscale(Rb.e, -Rb.s), j11b = zscale(Rb.e, Rb.c);
+            const Z t00 = zadd(zmul(m00, j00b), zmul(m01, j10b));
+            const Z t01 = zadd(zmul(m00, j01b), zmul(m01, j11b));
+            const Z t10 = zadd(zmul(m10, j00b), zmul(m11, j10b));
+            const Z t11 = zadd(zmul(m10, j01b), zmul(m11, j11b));
+            // A' = J_a^H T
+            const Z c00{Ra.c, 0.0}, c10 = zconj(zscale(Ra.e, -Ra.s));
+            const Z c01{Ra.s, 0.0}, c11 = zconj(zscale(Ra.e, Ra.c));
+            A2[(int64_t)pa * n + pb] = zadd(zmul(c00, t00), zmul(c10, t10));
+            if (qb_ok) A2[(int64_t)pa * n + qb] = zadd(zmul(c00, t01), zmul(c10, t11));
+            if (qa_ok) A2[(int64_t)qa * n + pb] = zadd(zmul(c01, t00), zmul(c11, t10));
+            if (qa_ok && qb_ok)
+                A2[(int64_t)qa * n + qb] = zadd(zmul(c01, t01), zmul(c11, t11));
+        } else {
+            const int64_t u = t - nblk;
+            const int i = (int)(u / h), kb = (int)(u - (int64_t)i * h);
+            int pb, qb;
+            rr_pair(m, round, kb, pb, qb);
+            const Rot Rb = make_rot(A, n, pb, qb);
+            const Z vp = V[(int64_t)i * n + pb];
+            if (qb >= n) {
+                V2[(int64_t)i * n + pb] = vp;
+                continue;
+            }
+            const Z vq = V[(int64_t)i * n + qb];
+            const Z j10b = zscale(Rb.e, -Rb.s), j11b = zscale(Rb.e, Rb.c);
+            V2[(int64_t)i * n + pb] = zadd(zscale(vp, Rb.c), zmul(vq, j10b));
+            V2[(int64_t)i * n + qb] = zadd(zscale(vp, Rb.s), zmul(vq, j11b));
+        }
+    }
+}
+
+// off^2 = sum_{i != j} |A_ij|^2 and tot^2 = sum |A_ij|^2 (one workgroup,
+// fixed order).
+__global__ __launch_bounds__(1024) void k_offnorm(const Z *__restrict__ A,
+                                                  int n, double *out) {
+    __shared__ double s1[1024], s2[1024];
+    const int t = threadIdx.x;
+    double off = 0.0, tot = 0.0;
+    for (int64_t e = t; e < (int64_t)n * n; e += 1024) {
+        const Z v = A[e];
+        const double m = v.x * v.x + v.y * v.y;
+        tot += m;
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (i != j) off += m;
+    }
+    s1[t] = off;
+    s2[t] = tot;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (t < s) {
+            s1[t] += s1[t + s];
+            s2[t] += s2[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = s1[0];
+        out[1] = s2[0];
+    }
+}
+
+__global__ void k_identity(Z *V, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        V[e] = Z{i == j ? 1.0 : 0.0, 0.0};
+    }
+}
+
+// Ascending order of the diagonal (ties keep index order): w[rank] and
+// Y[:, rank] = V[:, j].
+__global__ void k_sort_eig(const Z *__restrict__ A, const Z *__restrict__ V,
+                           int n, double *w, Z *Y) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += gridDim.x * blockDim.x) {
+        const double dj = A[(int64_t)j * n + j].x;
+        int rank = 0;
+        for (int i = 0; i < n; ++i) {
+            const double di = A[(int64_t)i * n + i].x;
+            rank += (di < dj) || (di == dj && i < j);
+        }
+        w[rank] = dj;
+        for (int i = 0; i < n; ++i) Y[(int64_t)i * n + rank] = V[(int64_t)i * n + j];
+    }
+}
+
+__global__ void k_hermitise(Z *G, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j < i) continue;
+        if (i == j) {
+            G[e].y = 0.0;
+            continue;
+        }
+        const Z a = G[e], b = G[(int64_t)j * n + i];
+        const Z m{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+        G[e] = m;
+        G[(int64_t)j * n + i] = Z{m.x, -m.y};
+    }
+}
+
+inline int grid_for(int64_t total) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+}
+
+}  // namespace
+
+void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, G, n, shift, B,
+                       work, info);
+    check_launch("k_chol_factor");
+}
+
+size_t jacobi_work_elems(int n) { return (size_t)3 * n * n; }
+
+void hermitise(Z *G, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_hermitise, dim3(grid_for((int64_t)n * n)), dim3(256),
+                       0, s, G, n);
+    check_launch("k_hermitise");
+}
+
+// A (overwritten) -> w ascending, Y eigenvectors.  work: 3 n^2 complex.
+// hwork: 2 doubles of pinned host memory for the convergence test.
+void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
+                hipStream_t s) {
+    Z *A2 = work;
+    Z *V = work + (size_t)n * n;
+    Z *V2 = work + (size_t)2 * n * n;
+    hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)n * n)), dim3(256), 0,
+                       s, V, n);
+    check_launch("k_identity");
+    if (n > 1) {
+        const int m = n + (n & 1);
+        const int h = m / 2;
+        const int grid = grid_for((int64_t)h * h + (int64_t)n * h);
+        double *dnorm = reinterpret_cast<double *>(Y);   // Y is free until the end
+        double prev = 1e300;
+        for (int sweep = 0; sweep < 30; ++sweep) {
+            for (int r = 0; r < m - 1; ++r) {
+                hipLaunchKernelGGL(k_jacobi_round, dim3(grid), dim3(256), 0, s, A,
+                                   A2, V, V2, n, m, r);
+                std::swap(A, A2);
+                std::swap(V, V2);
+            }
+            check_launch("k_jacobi_round");
+            hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, A, n, dnorm);
+            check_launch("k_offnorm");
+            CHASE_HIP(hipMemcpyAsync(hwork, dnorm, 2 * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            CHASE_HIP(hipStreamSynchronize(s));
+            const double off = std::sqrt(hwork[0]), tot = std::sqrt(hwork[1]);
+            if (!std::isfinite(off)) throw Error(5, "jacobi: non-finite matrix");
+            if (off <= 1e-15 * tot) break;
+            if (off <= 1e-12 * tot && off >= 0.5 * prev) break;   // rounding floor
+            prev = off;
+        }
+    }
+    hipLaunchKernelGGL(k_sort_eig, dim3((n + 255) / 256), dim3(256), 0, s, A, V,
+                       n, w, Y);
+    check_launch("k_sort_eig");
+}
+
+}  // namespace chase

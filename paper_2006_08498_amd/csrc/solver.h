@@ -1,0 +1,51 @@
+// The ChASE driver on one stream.
+#pragma once
+
+#include "../../include/chase_mi355x.h"
+#include "common.h"
+
+#include <vector>
+
+namespace chase {
+
+// Device workspace carved from one allocation (offsets in bytes).
+struct Layout {
+    int64_t N;
+    int ne, r, k;
+    size_t V, B1, W, T, fpart, gpart, G, Bq, cwork, Y, jwork, theta, resid,
+        npart, perm, info, Lv, Lvp, Lw, Lal, Lbe, total;
+};
+int internal_nex(int64_t N, int nev, int nex);
+Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o);
+
+struct Problem {
+    const Z *H;
+    int64_t N, ldh;
+    int nev, nex;
+    double tol;
+    int degree_max;
+    chase_opts opts;
+};
+
+struct Result {
+    std::vector<double> eigvals, resid;
+    chase_info info;
+    int status;   // CHASE_OK or CHASE_ENOCONV
+};
+
+// Runs the solve; eigenvectors (column-major, ldv) go to dV.
+Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv,
+             hipStream_t s);
+
+// Step-level helpers shared with the C ABI.
+void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
+                  int n, const int *deg, double mu1, double alpha, double beta,
+                  Z *fpart, hipStream_t s, std::vector<hipEvent_t> *prof);
+void qr_block(Z *V, Z *B1, int64_t ld, int64_t N, int L, int ne, Z *G, Z *Bq,
+              Z *cwork, Z *gpart, int *dinfo, hipStream_t s);
+void rr_block(const Z *H, int64_t ldh, int64_t N, Z *Q, Z *W, Z *T, Z *B1,
+              int64_t ld, int n, Z *G, Z *Y, Z *jwork, double *theta,
+              double *resid, Z *fpart, Z *gpart, double *npart, double *hwork,
+              hipStream_t s);
+
+}  // namespace chase

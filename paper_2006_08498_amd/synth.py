@@ -240,3 +240,92 @@ def gaussian_integer_hermitian(N, seed=0, lim=4):
 def colmajor(A):
     """Fortran-ordered copy: the byte layout of a column-major matrix."""
     return np.asfortranarray(A, dtype=np.complex128)
+
+
+# --------------------------------------------------------------------------
+# Device generators (large N): same definitions, evaluated by the HIP
+# kernels of libchase_synth.so.  torch supplies memory and the stream; the
+# planted family also uses torch's dense QR and matrix product on the device,
+# which build the input and are not part of the solver.
+# --------------------------------------------------------------------------
+
+_synth_lib = None
+
+
+def _slib():
+    global _synth_lib
+    if _synth_lib is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchase_synth.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: run paper_2006_08498_amd/build.py")
+        L = ctypes.CDLL(path)
+        P, I64, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+        L.synth_dk.restype = ctypes.c_int
+        L.synth_dk.argtypes = [P, I64, I64, ctypes.c_uint64, D, D, D, D, P]
+        L.synth_gauss.restype = ctypes.c_int
+        L.synth_gauss.argtypes = [P, I64, I64, I64, ctypes.c_uint64, ctypes.c_uint32, P]
+        L.synth_copy.restype = ctypes.c_int
+        L.synth_copy.argtypes = [P, P, I64, P]
+        _synth_lib = L
+    return _synth_lib
+
+
+def _stream():
+    import ctypes
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def dk_matrix_device(N, seed=0, std=0.02, decay=200.0, device="cuda"):
+    """D + K on the device, returned column-major (strides (1, N))."""
+    import ctypes
+    import torch
+    H = torch.empty((N, N), dtype=torch.complex128, device=device).t()
+    st = _slib().synth_dk(ctypes.c_void_p(H.data_ptr()), N, N, int(seed), std,
+                          decay, 1.0, 6.0, _stream())
+    if st != 0:
+        raise RuntimeError(f"synth_dk failed ({st})")
+    return H
+
+
+def gaussian_matrix_device(N, M, seed, stream=STREAM_GAUSS, device="cuda"):
+    """N x M complex Gaussian on the device, column-major (strides (1, N))."""
+    import ctypes
+    import torch
+    G = torch.empty((M, N), dtype=torch.complex128, device=device).t()
+    st = _slib().synth_gauss(ctypes.c_void_p(G.data_ptr()), N, N, M, int(seed),
+                             int(stream), _stream())
+    if st != 0:
+        raise RuntimeError(f"synth_gauss failed ({st})")
+    return G
+
+
+def planted_matrix_device(N, seed=0, lam=None, device="cuda", **spec):
+    """Planted-spectrum H on the device (row-major torch tensor) and its
+    eigenvalues; Q from the device QR of a Philox Gaussian matrix."""
+    import torch
+    if lam is None:
+        lam = planted_spectrum(N, seed, **spec)
+    G = gaussian_matrix_device(N, N, seed, device=device)
+    Q, R = torch.linalg.qr(G)
+    del G
+    d = torch.diagonal(R)
+    Q *= (d / d.abs())[None, :]
+    del R
+    lt = torch.as_tensor(np.asarray(lam), dtype=torch.float64, device=device)
+    H = (Q * lt[None, :]) @ Q.conj().t()
+    del Q
+    H = 0.5 * (H + H.conj().t())
+    return H.contiguous(), np.asarray(lam, dtype=np.float64)
+
+
+def device_copy(src, dst):
+    """Plain device copy kernel (traffic calibration for HBM counters)."""
+    import ctypes
+    n = src.numel() * src.element_size()
+    st = _slib().synth_copy(ctypes.c_void_p(src.data_ptr()),
+                            ctypes.c_void_p(dst.data_ptr()), n, _stream())
+    if st != 0:
+        raise RuntimeError(f"synth_copy failed ({st})")

@@ -1,0 +1,164 @@
+"""End-to-end parity of the GPU solver with the oracle (GPU, via the C ABI).
+
+Bar (per eigenpair): relative eigenvalue error <= 1e-10 against the oracle,
+||H v - lambda v|| / ||H||_2 <= 1e-10, max |V^H V - I| <= 1e-12, and the
+eigenvectors equal to the oracle's up to phase where eigenvalues are
+separated (cluster subspaces where they are not).
+"""
+import numpy as np
+import pytest
+
+from oracle import brute, eig
+from paper_2006_08498_amd import chase, synth
+from tests.gpu_util import dev_colmajor, host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_against_oracle(H, res, nev, hn=None):
+    w, V = res.eigvals, host(res.V)
+    N = H.shape[0]
+    m = min(nev + 1, N)
+    w_ext, V_ext = eig.eigh_lowest(H, m)
+    w_ref, V_ref = w_ext[:nev], V_ext[:, :nev]
+    if hn is None:
+        hn = np.abs(np.linalg.eigvalsh(H)).max()
+    assert np.all(np.abs(w - w_ref) <= 1e-10 * np.abs(w_ref) + 1e-300), np.abs(w - w_ref).max()
+    R = H @ V - V * w[None, :]
+    rn = np.linalg.norm(R, axis=0)
+    assert rn.max() / hn <= 1e-10
+    assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-12
+    # Eigenvectors: group eigenvalues closer than 1e-6 ||H|| into clusters
+    # and compare each cluster's subspace with the oracle's; by Davis-Kahan
+    # each side's angle to the exact subspace is at most its residual norm
+    # over the gap to the rest of the spectrum (a single vector is unique up
+    # to phase).  Computed residuals carry ~sqrt(N) u ||H|| of rounding.
+    rn_ref = np.linalg.norm(H @ V_ref - V_ref * w_ref[None, :], axis=0)
+    floor = 2.0 * np.sqrt(N) * 2.0 ** -53 * hn
+    start = 0
+    while start < nev:
+        end = start + 1
+        while end < nev and w_ref[end] - w_ref[end - 1] <= 1e-6 * hn:
+            end += 1
+        gap = np.inf
+        if start > 0:
+            gap = min(gap, w_ref[start] - w_ref[start - 1])
+        if end < m:
+            gap = min(gap, w_ext[end] - w_ext[end - 1])
+        A, B = V[:, start:end], V_ref[:, start:end]
+        d = np.linalg.norm(A @ (A.conj().T @ B) - B, 2)
+        k = end - start
+        r_both = (np.linalg.norm(rn[start:end]) + np.linalg.norm(rn_ref[start:end])
+                  + 2.0 * np.sqrt(k) * floor)
+        bound = 2.0 * r_both / max(gap, 1e-300) + 1e-13
+        assert d <= bound, (start, end, d, bound)
+        start = end
+    # Phase convention: the entry of largest modulus is real and positive.
+    for j in range(nev):
+        i = np.argmax(np.abs(V[:, j]))
+        assert V[i, j].imag == 0.0 and V[i, j].real > 0.0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dk_2000_matches_oracle(seed):
+    """The N = 2000 D + K workload (nev 20, nex 10, degree <= 20)."""
+    torch_cuda()
+    H = synth.dk_matrix(2000, seed=seed)
+    r = chase.solve(dev_colmajor(H), 20, 10, tol=1e-10, degree_max=20)
+    assert r.status == chase.CHASE_OK and r.info["nconv"] == 20
+    _check_against_oracle(H, r, 20)
+    assert 1 <= r.info["iterations"] <= 30
+    assert r.info["matvecs_filter"] > 0
+    assert r.info["beta"] >= np.linalg.eigvalsh(H)[-1]
+
+
+def test_row_major_input_gives_same_eigenpairs():
+    torch = torch_cuda()
+    H = synth.dk_matrix(800, seed=3)
+    rc = chase.solve(dev_colmajor(H), 8, 6)
+    rr = chase.solve(torch.from_numpy(H).cuda(), 8, 6)
+    assert np.abs(rc.eigvals - rr.eigvals).max() <= 1e-12
+    _check_against_oracle(H, rr, 8)
+
+
+@pytest.mark.parametrize("N,nev,nex", [(1, 1, 0), (2, 1, 1), (3, 2, 0), (8, 3, 2),
+                                       (40, 10, 30), (257, 7, 9), (1001, 12, 5)])
+def test_small_and_ragged_sizes(N, nev, nex):
+    torch_cuda()
+    if N <= 8:
+        H = synth.gaussian_integer_hermitian(N, seed=N).astype(np.complex128)
+        exact = np.array(brute.eigenvalues(H.tolist()))[:nev]
+    else:
+        H = synth.dk_matrix(N, seed=N)
+        exact = None
+    r = chase.solve(dev_colmajor(H), nev, nex, tol=1e-10, degree_max=20)
+    assert r.status == chase.CHASE_OK
+    _check_against_oracle(H, r, nev)
+    if exact is not None:
+        assert np.abs(r.eigvals - exact).max() <= 1e-10 * max(1.0, np.abs(exact).max())
+
+
+def test_planted_clusters():
+    torch_cuda()
+    N = 1500
+    H, lam, _ = synth.planted_matrix(N, seed=4, n_clusters=8, cluster_size=10)
+    nev, nex = 40, 16
+    r = chase.solve(dev_colmajor(H), nev, nex, tol=1e-10, degree_max=20)
+    assert r.status == chase.CHASE_OK
+    assert np.abs(r.eigvals - lam[:nev]).max() <= 1e-10 * lam[:nev].max()
+    _check_against_oracle(H, r, nev, hn=lam.max())
+
+
+def test_deterministic_repeat():
+    torch_cuda()
+    H = synth.dk_matrix(1200, seed=5)
+    dH = dev_colmajor(H)
+    a = chase.solve(dH, 10, 6)
+    b = chase.solve(dH, 10, 6)
+    assert np.array_equal(a.eigvals, b.eigvals)
+    assert np.array_equal(host(a.V), host(b.V))
+    for key in ("iterations", "matvecs_filter", "matvecs_total"):
+        assert a.info[key] == b.info[key]
+
+
+def test_warm_start_converges_fast():
+    torch = torch_cuda()
+    H = synth.dk_matrix(900, seed=6)
+    nev, nex = 10, 5
+    w, V = eig.eigh_lowest(H, nev + nex)
+    r = chase.solve(dev_colmajor(H), nev, nex, V0=torch.from_numpy(V).cuda())
+    assert r.status == chase.CHASE_OK and r.info["iterations"] <= 2
+    _check_against_oracle(H, r, nev)
+
+
+def test_failure_modes():
+    torch = torch_cuda()
+    H = synth.dk_matrix(300, seed=7)
+    Hn = H.copy()
+    Hn[17, 5] = np.nan
+    Hn[5, 17] = np.nan
+    with pytest.raises(chase.ChaseError) as ei:
+        chase.solve(dev_colmajor(Hn), 5, 3)
+    assert ei.value.status == chase.CHASE_ENONFINITE
+    r = chase.solve(dev_colmajor(H), 5, 3, max_iter=1, initial_degree=2,
+                    allow_noconv=True)
+    assert r.status == chase.CHASE_ENOCONV and r.info["nconv"] < 5
+    assert np.all(np.isfinite(r.eigvals)) and np.all(np.diff(r.eigvals) >= 0)
+    with pytest.raises(chase.ChaseError) as ei:
+        chase.solve(dev_colmajor(H), 200, 150)
+    assert ei.value.status == chase.CHASE_EINVAL
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(chase.ChaseError) as ei:
+        chase.solve(dev_colmajor(H), 5, 3, workspace=small)
+    assert ei.value.status == chase.CHASE_ENOMEM
+
+
+def test_caller_workspace_and_profile_counters():
+    torch = torch_cuda()
+    H = synth.dk_matrix(1000, seed=8)
+    nbytes = chase.workspace_bytes(1000, 10, 6)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    r = chase.solve(dev_colmajor(H), 10, 6, workspace=ws, profile=1)
+    _check_against_oracle(H, r, 10)
+    assert r.info["filter_launches"] > 0 and r.info["t_filter_kernels"] > 0
+    assert r.info["filter_flops"] == 8.0 * 1000 * 1000 * r.info["matvecs_filter"]
