@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times): "
+                         "the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
@@ -115,6 +118,17 @@ def main():
 
     import torch
     from paper_2006_08498_amd import chase
+
+    if args.copy_probe_mib:
+        from paper_2006_08498_amd import synth
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            synth.device_copy(a, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+        return
 
     w = WORKLOADS[args.workload]
     N, nev, nex = w["N"], w["nev"], w["nex"]

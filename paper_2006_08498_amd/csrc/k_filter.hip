@@ -23,146 +23,17 @@
 //    splits) are given ids on the same XCD and share that XCD's L2.
 #include "common.h"
 
+#include "k_filter_kern.h"
+
 namespace chase {
+
+void launch_filter_wide(const FilterPlan &p, const Z *H, int64_t ldh, int N,
+                        const Z *Y, int64_t ldy, const Z *X, int64_t ldx, Z *W,
+                        int64_t ldw, int n, double a, double b, double g, Z *part,
+                        hipStream_t s);
+
 namespace {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-template <int WN, bool FUSED>
-__global__ __launch_bounds__(256) void k_filter(
-    const Z *__restrict__ H, int64_t ldh, int N, const Z *__restrict__ Y,
-    int64_t ldy, const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
-    double b, double g, int rb_count, int cb_count, int splits, int kchunk,
-    Z *__restrict__ part) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int r = lane & 15, q = lane >> 4;
-
-    const int id = blockIdx.x;
-    const int xcd = id & 7;
-    const int local = id >> 3;
-    const int per = cb_count * splits;
-    const int rb = (local / per) * 8 + xcd;
-    if (rb >= rb_count) return;
-    const int rem = local % per;
-    const int cb = rem % cb_count;
-    const int sp = rem / cb_count;
-    const int row0 = rb * 64 + wave * 16;
-    if (row0 >= N) return;
-    const int col0 = cb * 16 * WN;
-    const int kbeg = sp * kchunk;
-    const int kend = min(N, kbeg + kchunk);
-
-    // Rows past N and columns past n are computed on clamped (valid)
-    // addresses and never stored.
-    const int arow = min(row0 + r, N - 1);
-    const Z *hp = H + arow + (int64_t)(kbeg + q) * ldh;
-    const int64_t hstep = 4 * ldh;
-    int ycol[WN];
-#pragma unroll
-    for (int c = 0; c < WN; ++c) ycol[c] = min(col0 + 16 * c + r, n - 1);
-    const Z *yp = Y + (int64_t)(kbeg + q) * ldy;
-    const int64_t ystep = 4 * ldy;
-
-    v4d cr[WN], ci[WN];
-#pragma unroll
-    for (int c = 0; c < WN; ++c) {
-        cr[c] = v4d{0.0, 0.0, 0.0, 0.0};
-        ci[c] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-
-    const int kfull = kbeg + ((kend - kbeg) & ~3);
-    int k = kbeg;
-    if (k < kfull) {
-        // Software pipeline: operands of step k+4 load while step k computes.
-        Z h = *hp;
-        Z y[WN];
-#pragma unroll
-        for (int c = 0; c < WN; ++c) y[c] = yp[ycol[c]];
-        for (; k + 4 < kfull; k += 4) {
-            hp += hstep;
-            yp += ystep;
-            Z hn = *hp;
-            Z yn[WN];
-#pragma unroll
-            for (int c = 0; c < WN; ++c) yn[c] = yp[ycol[c]];
-            const double nhy = -h.y;
-#pragma unroll
-            for (int c = 0; c < WN; ++c) cr[c] = mfma64(h.x, y[c].x, cr[c]);
-#pragma unroll
-            for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.x, y[c].y, ci[c]);
-#pragma unroll
-            for (int c = 0; c < WN; ++c) cr[c] = mfma64(nhy, y[c].y, cr[c]);
-#pragma unroll
-            for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.y, y[c].x, ci[c]);
-            h = hn;
-#pragma unroll
-            for (int c = 0; c < WN; ++c) y[c] = yn[c];
-        }
-        const double nhy = -h.y;
-#pragma unroll
-        for (int c = 0; c < WN; ++c) cr[c] = mfma64(h.x, y[c].x, cr[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.x, y[c].y, ci[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) cr[c] = mfma64(nhy, y[c].y, cr[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.y, y[c].x, ci[c]);
-        hp += hstep;
-        yp += ystep;
-        k = kfull;
-    }
-    if (k < kend) {
-        // Ragged tail of K: lanes whose k is past the end contribute zero
-        // and do not load.
-        const bool ok = (k + q) < kend;
-        Z h = ok ? *hp : Z{0.0, 0.0};
-        Z y[WN];
-#pragma unroll
-        for (int c = 0; c < WN; ++c) y[c] = ok ? yp[ycol[c]] : Z{0.0, 0.0};
-        const double nhy = -h.y;
-#pragma unroll
-        for (int c = 0; c < WN; ++c) cr[c] = mfma64(h.x, y[c].x, cr[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.x, y[c].y, ci[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) cr[c] = mfma64(nhy, y[c].y, cr[c]);
-#pragma unroll
-        for (int c = 0; c < WN; ++c) ci[c] = mfma64(h.y, y[c].x, ci[c]);
-    }
-
-    // Accumulator layout of the 16x16 FP64 MFMA: lane (r, q) holds rows
-    // q, q+4, q+8, q+12 of column r (register v holds row q + 4v).
-#pragma unroll
-    for (int c = 0; c < WN; ++c) {
-        const int col = col0 + 16 * c + r;
-        if (col >= n) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = row0 + q + 4 * v;
-            if (row >= N) continue;
-            const double sr = cr[c][v], si = ci[c][v];
-            if (FUSED) {
-                const Z yv = Y[(int64_t)row * ldy + col];
-                Z o;
-                o.x = a * sr + b * yv.x;
-                o.y = a * si + b * yv.y;
-                if (g != 0.0) {
-                    const Z xv = X[(int64_t)row * ldx + col];
-                    o.x += g * xv.x;
-                    o.y += g * xv.y;
-                }
-                W[(int64_t)row * ldw + col] = o;
-            } else {
-                part[((int64_t)sp * N + row) * n + col] = Z{sr, si};
-            }
-        }
-    }
-}
+using namespace filter_detail;
 
 // Ordered sum of the split-K partials plus the recurrence epilogue.
 __global__ __launch_bounds__(256) void k_filter_reduce(
@@ -193,23 +64,6 @@ __global__ __launch_bounds__(256) void k_filter_reduce(
     }
 }
 
-template <int WN>
-void launch_wn(const FilterPlan &p, const Z *H, int64_t ldh, int N, const Z *Y,
-               int64_t ldy, const Z *X, int64_t ldx, Z *W, int64_t ldw, int n,
-               double a, double b, double g, Z *part, hipStream_t s) {
-    const int groups = (p.rb + 7) / 8;
-    const int nblocks = groups * 8 * p.cb * p.splits;
-    if (p.splits == 1) {
-        hipLaunchKernelGGL((k_filter<WN, true>), dim3(nblocks), dim3(256), 0, s,
-                           H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, p.rb,
-                           p.cb, 1, p.kchunk, nullptr);
-    } else {
-        hipLaunchKernelGGL((k_filter<WN, false>), dim3(nblocks), dim3(256), 0,
-                           s, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g,
-                           p.rb, p.cb, p.splits, p.kchunk, part);
-    }
-}
-
 }  // namespace
 
 FilterPlan filter_plan(int64_t N, int n) {
@@ -223,18 +77,22 @@ FilterPlan filter_plan(int64_t N, int n) {
         p.wn = (nb16 + p.cb - 1) / p.cb;
     }
     p.rb = (int)((N + 63) / 64);
-    // Balance: workgroup slots ~ 256 CUs x (2 resident workgroups when the
-    // accumulators leave room for two waves per SIMD).
-    const int64_t slots = 256 * (p.wn <= 8 ? 2 : 1);
+    // K splits balance the workgroups over the 256 CUs.  Resident
+    // workgroups per CU = waves per SIMD of the tile's register budget
+    // (hipcc resource usage for gfx950); a round of `slots` workgroups runs
+    // concurrently, and a workgroup's time falls as 1/splits.  Splitting
+    // costs a partial-sum pass (2 * splits * N * n * 16 bytes), charged at
+    // 2% per split.
+    static const int occ[11] = {0, 3, 2, 2, 2, 2, 2, 1, 1, 1, 1};
+    const int64_t slots = 256 * (int64_t)occ[p.wn];
     const int64_t units = (int64_t)p.rb * p.cb;
-    const int cand[] = {1, 2, 3, 4, 6, 8};
     double best = 1e300;
     int bests = 1;
-    for (int sp : cand) {
-        if (sp > 1 && N / sp < 1024) break;
+    for (int sp = 1; sp <= 16; ++sp) {
+        if (sp > 1 && N / sp < 512) break;
         const double rounds = (double)((units * sp + slots - 1) / slots);
-        const double cost = rounds / sp * (1.0 + 0.01 * (sp - 1));
-        if (cost < best * 0.97) {
+        const double cost = rounds / sp + 0.02 * (sp - 1);
+        if (cost < best - 1e-12) {
             best = cost;
             bests = sp;
         }
@@ -262,8 +120,12 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N64, const Z *Y, int64_t ldy,
     switch (p.wn) {
 #define CASE(w) \
     case w: launch_wn<w>(p, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, part, s); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
+        case 9:
+        case 10:
+            launch_filter_wide(p, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, part, s);
+            break;
         default: throw Error(7, "filter_gemm: bad tile width");
     }
     check_launch("k_filter");
