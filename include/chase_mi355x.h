@@ -50,6 +50,8 @@ extern "C" {
 /* complex128, layout-compatible with std::complex<double> and numpy/torch
  * complex128 */
 typedef struct { double re, im; } chase_z;
+/* complex64, layout-compatible with numpy/torch complex64 (mixed precision) */
+typedef struct { float re, im; } chase_c;
 
 enum chase_status {
     CHASE_PENDING = -1,    /* server: request not finished yet */
@@ -106,7 +108,11 @@ typedef struct chase_info {
     double t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds */
     double t_filter_kernels;   /* sum of filter kernel durations (profile) */
     double filter_flops;       /* algorithmic filter flops, 8 N^2 per
-                                  column product */
+                                  column product (both precisions) */
+    double t_shadow;           /* CHASE_MIXED: building the complex64 copy
+                                  of H (seconds) */
+    double t_filter32_kernels; /* FP32 filter kernel durations (profile) */
+    int64_t filter32_launches; /* FP32 filter kernel launches */
 } chase_info;
 
 /* Fills *o with the defaults listed above. */
@@ -168,6 +174,23 @@ int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
                       const chase_z *dX, int64_t ldx,
                       chase_z *dW, int64_t ldw, int32_t ncols,
                       double a, double b, double g, void *stream);
+
+/*
+ * Mixed-precision form (filter with vectors above the switch tolerance):
+ * the same step in FP32 on the complex64 copy Hc of H (column-major, ldh)
+ * and complex64 row-major blocks, FP32 MFMA with FP32 accumulation.  dX may
+ * be NULL when g == 0; dW may equal dX, must not overlap dY.
+ */
+int chase_filter_step_c(const chase_c *dHc, int64_t N, int64_t ldh,
+                        const chase_c *dY, int64_t ldy, const chase_c *dX,
+                        int64_t ldx, chase_c *dW, int64_t ldw, int32_t ncols,
+                        float a, float b, float g, void *stream);
+
+/* Complex64 copy of H (each part rounded to nearest FP32), column-major
+ * with leading dimension ldc >= N; the solver builds it once per
+ * CHASE_MIXED solve. */
+int chase_shadow_c(const chase_z *dH, int64_t N, int64_t ldh, chase_c *dHc,
+                   int64_t ldc, void *stream);
 
 /*
  * The whole Chebyshev filter with per-vector degrees on an N x n block,

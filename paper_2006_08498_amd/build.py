@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
-SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_blas.hip", "k_dense.hip",
+SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_filter32.hip", "k_blas.hip", "k_dense.hip",
            "control.cpp", "solver.cpp", "capi.cpp"]
 # Input generators live in a library of their own: they are not the solver.
 SYNTH_SOURCES = ["synth_dev.hip"]
@@ -34,7 +34,8 @@ SYNTH_SOURCES = ["synth_dev.hip"]
 # MFMA register form per source: the VGPR form keeps the accumulators of the
 # narrower tiles in place; the widest filter tiles need the AGPR file.
 VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
-EXTRA = {"k_filter.hip": VGPR_FORM, "k_blas.hip": VGPR_FORM, "k_dense.hip": VGPR_FORM}
+EXTRA = {"k_filter.hip": VGPR_FORM, "k_filter32.hip": VGPR_FORM, "k_blas.hip": VGPR_FORM,
+         "k_dense.hip": VGPR_FORM}
 
 
 def _compile(src: str, verbose: bool) -> str:

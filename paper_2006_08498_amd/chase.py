@@ -78,6 +78,9 @@ class ChaseInfo(ctypes.Structure):
         ("t_total", ctypes.c_double),
         ("t_filter_kernels", ctypes.c_double),
         ("filter_flops", ctypes.c_double),
+        ("t_shadow", ctypes.c_double),
+        ("t_filter32_kernels", ctypes.c_double),
+        ("filter32_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -105,6 +108,10 @@ SIGNATURES = {
                                       ctypes.POINTER(ChaseOpts), ctypes.POINTER(ChaseInfo)]),
     "chase_filter_step": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
                                          _I32, _D, _D, _D, _P]),
+    "chase_filter_step_c": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
+                                           _I32, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, _P]),
+    "chase_shadow_c": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P]),
     "chase_filter": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _D, _D, _D,
                                     ctypes.POINTER(ctypes.c_int64), _P]),
     "chase_lanczos": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _P, _P, _P]),
@@ -268,6 +275,39 @@ def filter_step(H, Y, X, a, b, g, W=None, stream=None):
     wp, ldw = _block(W, "W")
     _check(lib().chase_filter_step(hp, N, ldh, yp, ldy, xp, ldx, wp, ldw, n,
                                    a, b, g, _stream_ptr(stream)))
+    return W
+
+
+def _block_c(t, name):
+    torch = _torch()
+    if t.dtype != torch.complex64 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major complex64 CUDA block")
+    return _dptr(t), t.stride(0)
+
+
+def shadow_c(H, stream=None):
+    """Complex64 copy of a column-major complex128 H (column-major result)."""
+    torch = _torch()
+    hp, ldh = _h_colmajor(H)
+    N = H.shape[0]
+    Hc = torch.empty((N, N), dtype=torch.complex64, device=H.device).t()
+    _check(lib().chase_shadow_c(hp, N, ldh, _dptr(Hc), N, _stream_ptr(stream)))
+    return Hc
+
+
+def filter_step_c(Hc, Y, X, a, b, g, W=None, stream=None):
+    """FP32 step W = a Hc Y + b Y + g X on complex64 blocks."""
+    torch = _torch()
+    if Hc.dtype != torch.complex64 or Hc.stride(0) != 1:
+        raise ValueError("Hc must be a column-major complex64 CUDA tensor")
+    N, n = Y.shape
+    yp, ldy = _block_c(Y, "Y")
+    xp, ldx = _block_c(X, "X") if X is not None else (None, n)
+    if W is None:
+        W = torch.empty_like(Y)
+    wp, ldw = _block_c(W, "W")
+    _check(lib().chase_filter_step_c(_dptr(Hc), N, Hc.stride(1), yp, ldy, xp, ldx, wp,
+                                     ldw, n, a, b, g, _stream_ptr(stream)))
     return W
 
 

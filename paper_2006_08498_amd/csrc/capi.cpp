@@ -92,7 +92,6 @@ chase_opts resolve(const chase_opts *o) {
 void validate_opts(const chase_opts &o) {
     REQUIRE(o.precision == CHASE_FP64 || o.precision == CHASE_MIXED,
             "unknown precision");
-    REQUIRE(o.precision == CHASE_FP64, "CHASE_MIXED is not available in this build");
     REQUIRE(o.max_iter >= 1, "max_iter must be >= 1");
     REQUIRE(o.initial_degree >= 1, "initial_degree must be >= 1");
     REQUIRE(o.degree_extra >= 0, "degree_extra must be >= 0");
@@ -197,6 +196,42 @@ int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
                     reinterpret_cast<const Z *>(dX), ldx,
                     reinterpret_cast<Z *>(dW), ldw, ncols, a, b, g,
                     part.as<Z>(), s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_filter_step_c(const chase_c *dHc, int64_t N, int64_t ldh,
+                        const chase_c *dY, int64_t ldy, const chase_c *dX,
+                        int64_t ldx, chase_c *dW, int64_t ldw, int32_t ncols,
+                        float a, float b, float g, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "bad N");
+        REQUIRE(ncols >= 0, "ncols must be >= 0");
+        REQUIRE(dHc && dY && dW, "NULL pointer");
+        REQUIRE(g == 0.0f || dX, "dX is NULL while g != 0");
+        REQUIRE(ldh >= N && ldy >= ncols && ldw >= ncols && (!dX || ldx >= ncols),
+                "bad leading dimension");
+        if (ncols == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        DevBuf part(filter32_partial_elems(N, ncols) * sizeof(C), s);
+        filter32_gemm(reinterpret_cast<const C *>(dHc), ldh, N,
+                      reinterpret_cast<const C *>(dY), ldy,
+                      reinterpret_cast<const C *>(dX), ldx,
+                      reinterpret_cast<C *>(dW), ldw, ncols, a, b, g, part.as<C>(), s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_shadow_c(const chase_z *dH, int64_t N, int64_t ldh, chase_c *dHc,
+                   int64_t ldc, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= (int64_t)1 << 31 && ldh >= N && ldc >= N, "bad sizes");
+        REQUIRE(dH && dHc, "NULL pointer");
+        hipStream_t s = S(stream);
+        z2c_matrix(reinterpret_cast<const Z *>(dH), ldh, reinterpret_cast<C *>(dHc), ldc,
+                   N, s);
         CHASE_HIP(hipStreamSynchronize(s));
         return CHASE_OK;
     });

@@ -10,6 +10,7 @@
 namespace chase {
 
 using Z = double2;   // complex128: .x = real, .y = imaginary
+using C = float2;    // complex64 (mixed-precision filter)
 
 // Error carried up to the C ABI, which turns it into a status code.
 struct Error : std::runtime_error {
@@ -51,6 +52,21 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N, const Z *Y, int64_t ldy,
                  const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
                  double b, double g, Z *part, hipStream_t s,
                  hipEvent_t after_mfma = nullptr);
+
+// FP32 filter GEMM on the complex64 shadow Hc (mixed precision), same
+// contract as filter_gemm; partials: filter32_partial_elems(N, n) complex64.
+FilterPlan filter32_plan(int64_t N, int n);
+size_t filter32_partial_elems(int64_t N, int n);
+void filter32_gemm(const C *H, int64_t ldh, int64_t N, const C *Y, int64_t ldy,
+                   const C *X, int64_t ldx, C *W, int64_t ldw, int n, float a,
+                   float b, float g, C *part, hipStream_t s,
+                   hipEvent_t after_mfma = nullptr);
+// Conversions: H (column-major) -> complex64 shadow; row-major blocks.
+void z2c_matrix(const Z *H, int64_t ldh, C *Hc, int64_t ldc, int64_t N, hipStream_t s);
+void z2c_block(const Z *V, int64_t ldv, C *Vc, int64_t ldc, int64_t N, int n,
+               hipStream_t s);
+void c2z_block(const C *Vc, int64_t ldc, Z *V, int64_t ldv, int64_t N, int n,
+               hipStream_t s);
 
 // C (p x q, row-major ldc) = A^H B over N rows; A: N x p, B: N x q.
 // `part` holds gram_partial_elems(N, p, q) elements of split-K partials.

@@ -70,6 +70,16 @@ Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o) {
     L.Lw = take((size_t)N * L.r * zb);
     L.Lal = take((size_t)L.k * L.r * sizeof(double));
     L.Lbe = take((size_t)L.k * L.r * sizeof(double));
+    L.mixed = o.precision == CHASE_MIXED;
+    L.Hc = L.Vc = L.Bc = L.fpart32 = 0;
+    if (L.mixed) {
+        size_t f32 = 0;
+        for (int n = 1; n <= ne; ++n) f32 = std::max(f32, filter32_partial_elems(N, n));
+        L.Hc = take((size_t)N * N * sizeof(C));
+        L.Vc = take((size_t)N * ne * sizeof(C));
+        L.Bc = take((size_t)N * ne * sizeof(C));
+        L.fpart32 = take(f32 * sizeof(C));
+    }
     L.total = off;
     return L;
 }
@@ -97,6 +107,52 @@ void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
             CHASE_HIP(hipEventRecord(e0, s));
         }
         filter_gemm(H, ldh, N, Y, ld, X, ld, W, ld, cols, a, b, g, fpart, s, e1);
+        if (prof) {
+            CHASE_HIP(hipEventRecord(e2, s));
+            prof->push_back(e0);
+            prof->push_back(e1);
+            prof->push_back(e2);
+        }
+    };
+    {
+        const double a = sigma1 / e;
+        launch(V, nullptr, B1, n, a, -c * a, 0.0);
+    }
+    double sprev = sigma1;
+    int first = 0;
+    for (int st = 2; st <= mmax; ++st) {
+        const double sigma = 1.0 / (tau - sprev);
+        const double a = 2.0 * sigma / e;
+        const double g = -sprev * sigma;
+        while (first < n && deg[first] < st) ++first;
+        const int cols = n - first;
+        if (st % 2 == 0) launch(B1 + first, V + first, V + first, cols, a, -c * a, g);
+        else launch(V + first, B1 + first, B1 + first, cols, a, -c * a, g);
+        sprev = sigma;
+    }
+}
+
+// Same recurrence on complex64 blocks with the complex64 shadow of H: the
+// coefficients are formed in FP64 and rounded once to FP32.
+void filter32_block(const C *Hc, int64_t N, C *V, C *B1, int64_t ld, int n,
+                    const int *deg, double mu1, double alpha, double beta,
+                    C *fpart, hipStream_t s, std::vector<hipEvent_t> *prof) {
+    if (n <= 0) return;
+    const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+    const double sigma1 = e / (mu1 - c);
+    const double tau = 2.0 / sigma1;
+    const int mmax = deg[n - 1];
+    auto launch = [&](const C *Y, const C *X, C *W, int cols, double a, double b,
+                      double g) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (prof) {
+            CHASE_HIP(hipEventCreate(&e0));
+            CHASE_HIP(hipEventCreate(&e1));
+            CHASE_HIP(hipEventCreate(&e2));
+            CHASE_HIP(hipEventRecord(e0, s));
+        }
+        filter32_gemm(Hc, N, N, Y, ld, X, ld, W, ld, cols, (float)a, (float)b,
+                      (float)g, fpart, s, e1);
         if (prof) {
             CHASE_HIP(hipEventRecord(e2, s));
             prof->push_back(e0);
@@ -257,6 +313,10 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     Z *Lw = reinterpret_cast<Z *>(base + Lo.Lw);
     double *Lal = reinterpret_cast<double *>(base + Lo.Lal);
     double *Lbe = reinterpret_cast<double *>(base + Lo.Lbe);
+    C *Hc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Hc) : nullptr;
+    C *Vc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Vc) : nullptr;
+    C *Bc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Bc) : nullptr;
+    C *fpart32 = Lo.mixed ? reinterpret_cast<C *>(base + Lo.fpart32) : nullptr;
 
     const int r = Lo.r, k = Lo.k;
     HostBuf hb((size_t)2 * k * r + 4 * (size_t)ne + 16);
@@ -269,8 +329,19 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     std::memset(&R.info, 0, sizeof(R.info));
     chase_info &info = R.info;
     Events E;
-    std::vector<hipEvent_t> prof;
+    std::vector<hipEvent_t> prof, prof32;
     std::vector<hipEvent_t> *profp = o.profile ? &prof : nullptr;
+    std::vector<hipEvent_t> *prof32p = o.profile ? &prof32 : nullptr;
+
+    // ---------------- mixed precision: complex64 shadow of H, once per solve
+    if (Lo.mixed) {
+        hipEvent_t z0 = E.make(), z1 = E.make();
+        CHASE_HIP(hipEventRecord(z0, s));
+        z2c_matrix(p.H, p.ldh, Hc, N, N, s);
+        CHASE_HIP(hipEventRecord(z1, s));
+        CHASE_HIP(hipEventSynchronize(z1));
+        info.t_shadow = elapsed(z0, z1);
+    }
     auto drain_prof = [&]() {
         // Events come in triples around each filter GEMM: before the MFMA
         // kernel, after it (before any split-K reduction), after the step.
@@ -280,6 +351,12 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         }
         for (auto e : prof) (void)hipEventDestroy(e);
         prof.clear();
+        for (size_t i = 0; i + 3 <= prof32.size(); i += 3) {
+            info.t_filter32_kernels += elapsed(prof32[i], prof32[i + 1]);
+            info.filter32_launches += 1;
+        }
+        for (auto e : prof32) (void)hipEventDestroy(e);
+        prof32.clear();
     };
 
     // ---------------- Lanczos: spectral bounds (once per solve)
@@ -322,6 +399,12 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     d0 += d0 % 2;
     std::vector<int> deg(ne, d0), hperm(ne);
     std::vector<double> lam(ne, 0.0), res(ne, INFINITY);
+    // Mixed precision: a column is filtered in FP32 while its residual is
+    // above switch_tol * ||H|| and FP32 still improves it (a column whose
+    // FP32 iteration gained less than 10x moves to FP64 for good).
+    const double sw_abs = o.switch_tol * bd.hnorm;
+    std::vector<char> fp32(ne, Lo.mixed ? 1 : 0), use64(ne, 0);
+    std::vector<double> res_prev(ne, INFINITY), pred_gain(ne, 1.0);
     int L = 0;
     int it = 0;
     int qr_salt = 0;
@@ -334,8 +417,18 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         // When the search space is the whole space (ne == N) Rayleigh-Ritz
         // is exact and filtering would only make the block ill-conditioned.
         if (ne < N && e_half > 1e-14 * std::max(1.0, std::fabs(beta))) {
-            filter_block(p.H, p.ldh, N, V + L, B1 + L, ne, n, deg.data() + L, mu1,
-                         alpha, beta, fpart, s, profp);
+            // Active columns: the FP32 group first, each group by degree.
+            int n32 = 0;
+            while (n32 < n && fp32[L + n32]) ++n32;
+            if (n32 > 0) {
+                z2c_block(V + L, ne, Vc, n32, N, n32, s);
+                filter32_block(Hc, N, Vc, Bc, n32, n32, deg.data() + L, mu1, alpha,
+                               beta, fpart32, s, prof32p);
+                c2z_block(Vc, n32, V + L, ne, N, n32, s);
+                for (int j = L; j < L + n32; ++j) info.matvecs_filter_fp32 += deg[j];
+            }
+            filter_block(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne, n - n32,
+                         deg.data() + L + n32, mu1, alpha, beta, fpart, s, profp);
             for (int j = L; j < ne; ++j) info.matvecs_filter += deg[j];
         }
         CHASE_HIP(hipEventRecord(ev[1], s));
@@ -379,11 +472,28 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         alpha = h_th[n - 1];
         mu1 = std::min(mu1, h_th[0]);
         const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
-        for (int j = L; j < ne; ++j)
-            deg[j] = degree_for(res[j], tol_abs, lam[j], c, e, p.degree_max, o.degree_extra);
+        for (int j = L; j < ne; ++j) {
+            if (Lo.mixed) {
+                // FP32 has stalled on this vector if its residual fell by
+                // less than a quarter of the orders of magnitude the filter
+                // rate predicted (rho^m); it is then filtered in FP64.
+                if (fp32[j] && std::isfinite(res_prev[j]) && pred_gain[j] >= 100.0 &&
+                    res_prev[j] / res[j] < std::pow(pred_gain[j], 0.25))
+                    use64[j] = 1;
+                res_prev[j] = res[j];
+                fp32[j] = (!use64[j] && res[j] > sw_abs) ? 1 : 0;
+            }
+            // FP32 vectors aim at the switch level, FP64 ones at tol.
+            const double target = fp32[j] ? std::max(tol_abs, 0.1 * sw_abs) : tol_abs;
+            deg[j] = degree_for(res[j], target, lam[j], c, e, p.degree_max, o.degree_extra);
+            pred_gain[j] = std::pow(rate(lam[j], c, e), (double)deg[j]);
+        }
         std::vector<int> idx(ne - L);
         std::iota(idx.begin(), idx.end(), L);
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            if (fp32[a] != fp32[b]) return fp32[a] > fp32[b];
+            return deg[a] < deg[b];
+        });
         bool ident = true;
         for (int j = 0; j < ne - L; ++j) {
             hperm[j] = idx[j] - L;
@@ -395,16 +505,25 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
             permute_cols(V + L, ne, B1 + L, ne, N, ne - L, perm, s);
             copy_block(B1 + L, ne, V + L, ne, N, ne - L, s);
             std::vector<int> d2(ne - L);
-            std::vector<double> l2(ne - L), r2(ne - L);
+            std::vector<double> l2(ne - L), r2(ne - L), p2(ne - L), g2(ne - L);
+            std::vector<char> f2(ne - L), u2(ne - L);
             for (int j = 0; j < ne - L; ++j) {
                 d2[j] = deg[idx[j]];
                 l2[j] = lam[idx[j]];
                 r2[j] = res[idx[j]];
+                p2[j] = res_prev[idx[j]];
+                g2[j] = pred_gain[idx[j]];
+                f2[j] = fp32[idx[j]];
+                u2[j] = use64[idx[j]];
             }
             for (int j = 0; j < ne - L; ++j) {
                 deg[L + j] = d2[j];
                 lam[L + j] = l2[j];
                 res[L + j] = r2[j];
+                res_prev[L + j] = p2[j];
+                pred_gain[L + j] = g2[j];
+                fp32[L + j] = f2[j];
+                use64[L + j] = u2[j];
             }
             // hperm is read by the copy above before the next host write
             CHASE_HIP(hipStreamSynchronize(s));

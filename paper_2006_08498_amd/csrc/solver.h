@@ -13,7 +13,12 @@ struct Layout {
     int64_t N;
     int ne, r, k;
     size_t V, B1, W, T, fpart, gpart, G, Bq, cwork, Y, jwork, theta, resid,
-        npart, perm, info, Lv, Lvp, Lw, Lal, Lbe, total;
+        npart, perm, info, Lv, Lvp, Lw, Lal, Lbe;
+    // CHASE_MIXED only (size 0 otherwise): complex64 shadow of H, two FP32
+    // vector blocks and the FP32 split-K partials.
+    size_t Hc, Vc, Bc, fpart32;
+    bool mixed;
+    size_t total;
 };
 int internal_nex(int64_t N, int nev, int nex);
 Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o);
@@ -41,6 +46,9 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv,
 void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
                   int n, const int *deg, double mu1, double alpha, double beta,
                   Z *fpart, hipStream_t s, std::vector<hipEvent_t> *prof);
+void filter32_block(const C *Hc, int64_t N, C *V, C *B1, int64_t ld, int n,
+                    const int *deg, double mu1, double alpha, double beta,
+                    C *fpart, hipStream_t s, std::vector<hipEvent_t> *prof);
 void qr_block(Z *V, Z *B1, int64_t ld, int64_t N, int L, int ne, Z *G, Z *Bq,
               Z *cwork, Z *gpart, int *dinfo, hipStream_t s);
 void rr_block(const Z *H, int64_t ldh, int64_t N, Z *Q, Z *W, Z *T, Z *B1,
