@@ -39,6 +39,126 @@ WORKLOADS = {
 }
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA (published)
 
+# Serving: 128 requests, Poisson arrivals at 4 per second (seed 42), N uniform
+# in {4000, ..., 20000}, nev uniform in [30, 150], nex = round-half-up(0.4
+# nev), D + K (std 0.02, decay 200) with seed 1000 + r, generated on the
+# device when the request is admitted.
+SERVE = dict(requests=128, rate=4.0, seed=42, sizes=(4000, 8000, 12000, 16000, 20000),
+             nev_range=(30, 150), nex_frac=0.4, std=0.02, decay=200.0, tol=1e-10,
+             degree_max=20)
+
+
+def serve_schedule(cfg):
+    """Arrival times and request shapes, from one seeded numpy generator."""
+    rng = np.random.default_rng(cfg["seed"])
+    n = cfg["requests"]
+    gaps = rng.exponential(1.0 / cfg["rate"], n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    Ns = rng.choice(np.array(cfg["sizes"]), n)
+    nevs = rng.integers(cfg["nev_range"][0], cfg["nev_range"][1] + 1, n)
+    nexs = np.floor(cfg["nex_frac"] * nevs + 0.5).astype(int)
+    return [dict(r=i, t=float(arrivals[i]), N=int(Ns[i]), nev=int(nevs[i]),
+                 nex=int(nexs[i]), seed=1000 + i) for i in range(n)]
+
+
+def run_serve(args):
+    """Continuous batching under a Poisson arrival schedule; p50/p99 latency
+    from submission to completion, throughput over the whole run."""
+    import ctypes
+    import torch
+    from paper_2006_08498_amd import chase, synth
+    cfg = SERVE
+    sched = serve_schedule(cfg)
+    slib = synth._slib()
+
+    def make_fill(seed):
+        def fill(ptr, n, ld, stream):
+            return slib.synth_dk(ctypes.c_void_p(ptr), ld, n, seed, cfg["std"],
+                                 cfg["decay"], 1.0, 6.0, ctypes.c_void_p(stream))
+        return fill
+
+    srv = chase.Server(budget_bytes=0, slots=args.slots)
+    log(f"serving {len(sched)} requests over {sched[-1]['t']:.1f} s with "
+        f"{args.slots} slots")
+    pending = {}
+    done = []
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(sched) or pending:
+        now = time.perf_counter() - t0
+        while i < len(sched) and sched[i]["t"] <= now:
+            q = sched[i]
+            tk = srv.submit_fill(make_fill(q["seed"]), q["N"], q["nev"], q["nex"],
+                                 cfg["tol"], cfg["degree_max"], profile=1)
+            pending[tk] = q
+            i += 1
+        for tk in list(pending):
+            res = srv.poll(tk)
+            if res is not None:
+                q = pending.pop(tk)
+                done.append((q, res, time.perf_counter() - t0))
+                if len(done) % 16 == 0:
+                    log(f"{len(done)} done, latency {res.latency_s:.2f} s, "
+                        f"stats {srv.stats()}")
+        time.sleep(0.002)
+    makespan = max(c for _, _, c in done) - sched[0]["t"]
+    peak = srv.stats()
+    srv.close()
+    lat = np.sort([r.latency_s for _, r, _ in done])
+    n = len(lat)
+    p50 = float(lat[int(np.ceil(0.50 * n)) - 1])
+    p99 = float(lat[int(np.ceil(0.99 * n)) - 1])
+    flops = sum(r.info["filter_flops"] for _, r, _ in done)
+    # Verify a sample of results against their matrices (regenerated).
+    worst = 0.0
+    for q, r, _ in done[:: max(1, n // 8)]:
+        H = synth.dk_matrix_device(q["N"], seed=q["seed"], std=cfg["std"], decay=cfg["decay"])
+        V = r.V
+        w = torch.as_tensor(r.eigvals, device="cuda")
+        R = H @ V - V * w[None, :]
+        rel = float(torch.linalg.vector_norm(R, dim=0).max()) / r.info["hnorm_est"]
+        worst = max(worst, rel)
+        del H
+    out = {
+        "metric": "p50/p99 solve latency",
+        "value": p50,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": 1e3 * makespan / n,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serve128: 128 requests, Poisson 4/s, N in {4k..20k} D+K, "
+                               "nev in [30,150], nex=0.4 nev, tol 1e-10, degree<=20",
+                   "slots": args.slots, "parallelism": "1 GPU"},
+        "p50_s": p50, "p99_s": p99,
+        "throughput_req_per_s": n / makespan,
+        "makespan_s": makespan,
+        "aggregate_filter_tflops": flops / makespan / 1e12,
+        "mean_queue_s": float(np.mean([r.queued_s for _, r, _ in done])),
+        "mean_gpu_s": float(np.mean([r.gpu_s for _, r, _ in done])),
+        "peak_running": peak["peak_running"], "peak_bytes": peak["peak_bytes"],
+        "check": {"max_resid_rel_sampled": worst},
+    }
+    if args.serve_solo_baseline:
+        # The same requests solved one after another, each alone on the GPU.
+        t_solo = 0.0
+        for q, _, _ in done:
+            H = synth.dk_matrix_device(q["N"], seed=q["seed"], std=cfg["std"],
+                                       decay=cfg["decay"])
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            chase.solve(H, q["nev"], q["nex"], cfg["tol"], cfg["degree_max"])
+            t_solo += time.perf_counter() - a
+            del H
+        out["solo_sum_s"] = t_solo
+        out["speedup_served_over_solo"] = t_solo / makespan
+    print(json.dumps(out), flush=True)
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -135,7 +255,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="planted24k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="planted24k",
+                    choices=sorted(WORKLOADS) + ["serve128"])
+    ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
+    ap.add_argument("--serve-solo-baseline", action="store_true",
+                    help="serve128: also time every request alone, one after another")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -162,6 +286,9 @@ def main():
             synth.device_copy(a, b)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+        return
+    if args.workload == "serve128":
+        run_serve(args)
         return
 
     w = WORKLOADS[args.workload]

@@ -270,6 +270,74 @@ int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
                   double tol_abs, double alpha, double beta,
                   int32_t degree_max, int32_t extra, int32_t *h_degrees);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of independent eigenproblems on one GPU (no source
+ * in the paper, which solves one matrix at a time; its workflows solve
+ * series of matrices, Sec. "A practical case: converging exciton-binding
+ * energy in naphthalene").  Requests of uneven N are admitted first-fit in
+ * arrival order as soon as a slot is free and their device footprint (H
+ * unless the caller holds it, the solver workspace and the eigenvector
+ * output) fits the memory budget; admitted requests run concurrently, one
+ * HIP stream per slot, with H and the subspace resident until the result is
+ * collected.  A request's result is bitwise the same alone and in the mix.
+ */
+typedef struct chase_server chase_server;
+
+/* Produces H for a request at admission: writes the N x N column-major
+ * complex128 matrix (leading dimension ldh) into dH (device memory the
+ * server owns) with work enqueued on `stream`; returns 0 on success.  Called
+ * from a server thread. */
+typedef int (*chase_fill_fn)(chase_z *dH, int64_t N, int64_t ldh, void *user,
+                             void *stream);
+
+/* hbm_budget_bytes: device memory the server may allocate (0 = free memory
+ * minus a reserve); max_slots: concurrent solves (1..64).  NULL on failure
+ * (chase_server_last_error()). */
+chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots);
+
+/* Queues a request.  H is a host matrix (copied now, uploaded at admission,
+ * counted in the footprint) when is_device == 0, else a caller-owned device
+ * matrix with ldh == N that must stay valid until the request is polled
+ * (not counted).  Options as for chase_solve_ex (no warm start).  Returns
+ * CHASE_ENOMEM if the footprint alone exceeds the budget. */
+int chase_server_submit(chase_server *srv, const chase_z *H, int is_device,
+                        int64_t N, int64_t ldh, int32_t nev, int32_t nex,
+                        double tol, int32_t degree_max, const chase_opts *o,
+                        uint64_t *ticket);
+
+/* Queues a request whose H is produced at admission by `fill` (counted in
+ * the footprint). */
+int chase_server_submit_fill(chase_server *srv, chase_fill_fn fill, void *user,
+                             int64_t N, int32_t nev, int32_t nex, double tol,
+                             int32_t degree_max, const chase_opts *o,
+                             uint64_t *ticket);
+
+/* CHASE_PENDING while the request is queued or running.  Otherwise copies
+ * the results (eigenvalues ascending into h_eigvals, residuals into h_resid
+ * if not NULL, eigenvectors column-major into dV with ldv >= N, info if not
+ * NULL, and if h_times3 is not NULL: seconds queued, seconds on the GPU,
+ * latency from submission to completion), releases the request and returns
+ * its status (CHASE_OK, CHASE_ENOCONV or the error). */
+int chase_server_poll(chase_server *srv, uint64_t ticket, double *h_eigvals,
+                      double *h_resid, chase_z *dV, int64_t ldv,
+                      chase_info *info, double *h_times3);
+
+/* Blocks until the request is done (timeout_s < 0: no timeout); CHASE_OK
+ * when done, CHASE_PENDING on timeout. */
+int chase_server_wait(chase_server *srv, uint64_t ticket, double timeout_s);
+
+/* Memory in use and its peak (bytes), running and peak running requests,
+ * queued requests.  Any pointer may be NULL. */
+int chase_server_stats(chase_server *srv, size_t *bytes_in_use,
+                       size_t *peak_bytes, int32_t *running,
+                       int32_t *peak_running, int32_t *queued);
+
+/* Message for the last server call that failed on this thread. */
+const char *chase_server_last_error(void);
+
+/* Drops queued requests, waits for running ones, frees everything. */
+void chase_server_destroy(chase_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -396,3 +396,138 @@ def degrees(theta, resid, tol_abs, alpha, beta, degree_max, extra=2):
                                tol_abs, alpha, beta, degree_max, extra,
                                out.ctypes.data_as(_P)))
     return out
+
+
+# ------------------------------------------------------------------ serving
+
+FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                           ctypes.c_void_p, ctypes.c_void_p)
+
+SIGNATURES.update({
+    "chase_server_create": (ctypes.c_void_p, [ctypes.c_size_t, _I32]),
+    "chase_server_submit": (ctypes.c_int, [_P, _P, ctypes.c_int, _I64, _I64, _I32, _I32, _D,
+                                           _I32, ctypes.POINTER(ChaseOpts),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "chase_server_submit_fill": (ctypes.c_int, [_P, FILL_FN, _P, _I64, _I32, _I32, _D, _I32,
+                                                ctypes.POINTER(ChaseOpts),
+                                                ctypes.POINTER(ctypes.c_uint64)]),
+    "chase_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _P, _P, _P, _I64,
+                                         ctypes.POINTER(ChaseInfo), _P]),
+    "chase_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, _D]),
+    "chase_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "chase_server_last_error": (ctypes.c_char_p, []),
+    "chase_server_destroy": (None, [_P]),
+})
+
+
+@dataclass
+class ServedResult:
+    eigvals: np.ndarray
+    resid: np.ndarray
+    V: object                 # torch (N, nev) complex128, column-major memory
+    status: int
+    info: dict
+    queued_s: float
+    gpu_s: float
+    latency_s: float
+
+
+class Server:
+    """Continuous-batching server (marshalling over chase_server_*).
+
+    ``submit(H, ...)`` takes a device tensor held by the caller until it is
+    polled (column-major, ldh == N); ``submit_fill(fill, N, ...)`` takes a
+    callable fill(ptr, N, ld, stream_ptr) -> int run at admission on the
+    slot's stream."""
+
+    def __init__(self, budget_bytes=0, slots=4):
+        L = lib()
+        self._s = L.chase_server_create(int(budget_bytes), int(slots))
+        if not self._s:
+            msg = L.chase_server_last_error()
+            raise ChaseError(CHASE_EINTERNAL, msg.decode() if msg else "create failed")
+        self._keep = {}      # ticket -> objects kept alive (tensors, callbacks)
+        self._shape = {}     # ticket -> (N, nev)
+
+    def _err(self):
+        msg = lib().chase_server_last_error()
+        return msg.decode() if msg else ""
+
+    def submit(self, H, nev, nex, tol=1e-10, degree_max=20, **opt_kw):
+        hp, ldh, conj = _h_layout(H)
+        if conj:
+            raise ValueError("server requests take H column-major (strides (1, N))")
+        N = H.shape[0]
+        o = default_opts(**opt_kw)
+        t = ctypes.c_uint64(0)
+        st = lib().chase_server_submit(self._s, hp, 1, N, ldh, nev, nex, tol, degree_max,
+                                       ctypes.byref(o), ctypes.byref(t))
+        if st != CHASE_OK:
+            raise ChaseError(st, self._err())
+        self._keep[t.value] = (H,)
+        self._shape[t.value] = (N, nev)
+        return t.value
+
+    def submit_fill(self, fill, N, nev, nex, tol=1e-10, degree_max=20, **opt_kw):
+        def _cb(ptr, n, ld, user, stream):
+            try:
+                return int(fill(ptr, n, ld, stream))
+            except Exception:  # noqa: BLE001 - reported as a status to C
+                return 1
+        cb = FILL_FN(_cb)
+        o = default_opts(**opt_kw)
+        t = ctypes.c_uint64(0)
+        st = lib().chase_server_submit_fill(self._s, cb, None, N, nev, nex, tol, degree_max,
+                                            ctypes.byref(o), ctypes.byref(t))
+        if st != CHASE_OK:
+            raise ChaseError(st, self._err())
+        self._keep[t.value] = (cb,)
+        self._shape[t.value] = (N, nev)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        return lib().chase_server_wait(self._s, ticket, float(timeout)) == CHASE_OK
+
+    def poll(self, ticket, allow_noconv=False):
+        """ServedResult when done, None while pending."""
+        torch = _torch()
+        N, nev = self._shape[ticket]
+        out = torch.empty((nev, N), dtype=torch.complex128, device="cuda")
+        ev = np.zeros(nev)
+        rs = np.zeros(nev)
+        info = ChaseInfo()
+        times = np.zeros(3)
+        st = lib().chase_server_poll(self._s, ticket, ev.ctypes.data_as(_P),
+                                     rs.ctypes.data_as(_P), _dptr(out), N,
+                                     ctypes.byref(info), times.ctypes.data_as(_P))
+        if st == CHASE_PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        self._shape.pop(ticket, None)
+        if st not in ((CHASE_OK, CHASE_ENOCONV) if allow_noconv else (CHASE_OK,)):
+            raise ChaseError(st, self._err())
+        return ServedResult(ev, rs, out.t(), st, info.as_dict(), *map(float, times))
+
+    def stats(self):
+        a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        c, d, e = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        lib().chase_server_stats(self._s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                 ctypes.byref(d), ctypes.byref(e))
+        return {"bytes_in_use": a.value, "peak_bytes": b.value, "running": c.value,
+                "peak_running": d.value, "queued": e.value}
+
+    def close(self):
+        if self._s:
+            lib().chase_server_destroy(self._s)
+            self._s = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

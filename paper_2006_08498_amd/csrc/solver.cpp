@@ -405,6 +405,8 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     const double sw_abs = o.switch_tol * bd.hnorm;
     std::vector<char> fp32(ne, Lo.mixed ? 1 : 0), use64(ne, 0);
     std::vector<double> res_prev(ne, INFINITY), pred_gain(ne, 1.0);
+    std::vector<int> rdeg(ne, d0);           // degrees in Ritz order
+    int n32 = Lo.mixed ? ne : 0;             // FP32 columns leading the filter order
     int L = 0;
     int it = 0;
     int qr_salt = 0;
@@ -418,8 +420,6 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         // is exact and filtering would only make the block ill-conditioned.
         if (ne < N && e_half > 1e-14 * std::max(1.0, std::fabs(beta))) {
             // Active columns: the FP32 group first, each group by degree.
-            int n32 = 0;
-            while (n32 < n && fp32[L + n32]) ++n32;
             if (n32 > 0) {
                 z2c_block(V + L, ne, Vc, n32, N, n32, s);
                 filter32_block(Hc, N, Vc, Bc, n32, n32, deg.data() + L, mu1, alpha,
@@ -468,7 +468,11 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         L += cnt;
         info.iterations = it;
         if (L >= nev || it == o.max_iter) break;
-        // Filter interval, rates and degrees for the next iteration.
+        // Filter interval, rates and degrees for the next iteration.  The
+        // per-vector state is kept in Ritz order (position j = j-th smallest
+        // Ritz value of the active block, as Rayleigh-Ritz returns it); only
+        // the filter's column order (FP32 group first, then ascending
+        // degree) is a permutation of it.
         alpha = h_th[n - 1];
         mu1 = std::min(mu1, h_th[0]);
         const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
@@ -485,46 +489,28 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
             }
             // FP32 vectors aim at the switch level, FP64 ones at tol.
             const double target = fp32[j] ? std::max(tol_abs, 0.1 * sw_abs) : tol_abs;
-            deg[j] = degree_for(res[j], target, lam[j], c, e, p.degree_max, o.degree_extra);
-            pred_gain[j] = std::pow(rate(lam[j], c, e), (double)deg[j]);
+            rdeg[j] = degree_for(res[j], target, lam[j], c, e, p.degree_max, o.degree_extra);
+            pred_gain[j] = std::pow(rate(lam[j], c, e), (double)rdeg[j]);
         }
         std::vector<int> idx(ne - L);
         std::iota(idx.begin(), idx.end(), L);
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
             if (fp32[a] != fp32[b]) return fp32[a] > fp32[b];
-            return deg[a] < deg[b];
+            return rdeg[a] < rdeg[b];
         });
         bool ident = true;
+        n32 = 0;
         for (int j = 0; j < ne - L; ++j) {
             hperm[j] = idx[j] - L;
             ident = ident && hperm[j] == j;
+            deg[L + j] = rdeg[idx[j]];
+            n32 += fp32[idx[j]] ? 1 : 0;
         }
         if (!ident) {
             CHASE_HIP(hipMemcpyAsync(perm, hperm.data(), sizeof(int) * (ne - L),
                                      hipMemcpyHostToDevice, s));
             permute_cols(V + L, ne, B1 + L, ne, N, ne - L, perm, s);
             copy_block(B1 + L, ne, V + L, ne, N, ne - L, s);
-            std::vector<int> d2(ne - L);
-            std::vector<double> l2(ne - L), r2(ne - L), p2(ne - L), g2(ne - L);
-            std::vector<char> f2(ne - L), u2(ne - L);
-            for (int j = 0; j < ne - L; ++j) {
-                d2[j] = deg[idx[j]];
-                l2[j] = lam[idx[j]];
-                r2[j] = res[idx[j]];
-                p2[j] = res_prev[idx[j]];
-                g2[j] = pred_gain[idx[j]];
-                f2[j] = fp32[idx[j]];
-                u2[j] = use64[idx[j]];
-            }
-            for (int j = 0; j < ne - L; ++j) {
-                deg[L + j] = d2[j];
-                lam[L + j] = l2[j];
-                res[L + j] = r2[j];
-                res_prev[L + j] = p2[j];
-                pred_gain[L + j] = g2[j];
-                fp32[L + j] = f2[j];
-                use64[L + j] = u2[j];
-            }
             // hperm is read by the copy above before the next host write
             CHASE_HIP(hipStreamSynchronize(s));
         }

@@ -1,0 +1,82 @@
+"""Serving (continuous batching) on the GPU, via the C ABI.
+
+Each request's result must be the same alone and in the mix (bitwise: every
+kernel reduces in a fixed order and each solve has its own workspace);
+admission must respect the memory budget; H may come from a caller buffer
+or be produced at admission by a fill callback."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2006_08498_amd import chase, synth
+from tests.gpu_util import dev_colmajor, host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(1500, 10, 4, 11), (2600, 20, 8, 12), (900, 8, 3, 13), (3000, 30, 12, 14)]
+
+
+def _solo(H, nev, nex):
+    return chase.solve(H, nev, nex, 1e-10, 20)
+
+
+def test_results_same_alone_and_in_the_mix():
+    torch_cuda()
+    mats = [dev_colmajor(synth.dk_matrix(N, seed=s)) for N, _, _, s in CASES]
+    solo = [_solo(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, CASES)]
+    with chase.Server(slots=3) as srv:
+        tickets = [srv.submit(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, CASES)]
+        outs = []
+        for t in tickets:
+            assert srv.wait(t, timeout=120.0)
+            outs.append(srv.poll(t))
+        st = srv.stats()
+    assert st["peak_running"] >= 2          # the work overlapped
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a.eigvals, b.eigvals)
+        assert np.array_equal(host(a.V), host(b.V))
+        assert a.info["iterations"] == b.info["iterations"]
+        assert b.latency_s >= b.gpu_s >= 0 and b.queued_s >= 0
+
+
+def test_budget_admits_one_at_a_time():
+    torch = torch_cuda()
+    same = [(2600, 20, 8, 31), (2600, 20, 8, 32), (2600, 20, 8, 33)]
+    mats = [dev_colmajor(synth.dk_matrix(N, seed=s)) for N, _, _, s in same]
+    # Budget for one footprint (H is the caller's, so: workspace, output and
+    # alignment slack): three equal requests must run one by one.
+    fp = chase.workspace_bytes(2600, 20, 8) + 16 * 2600 * 20 + 768
+    budget = fp + 4096
+    with chase.Server(budget_bytes=budget, slots=4) as srv:
+        tickets = [srv.submit(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, same)]
+        for t in tickets:
+            assert srv.wait(t, timeout=120.0)
+            srv.poll(t)
+        st = srv.stats()
+        assert st["peak_bytes"] <= budget
+        assert st["peak_running"] == 1
+        # A request whose footprint exceeds the budget is refused at once.
+        big = torch.empty((1, 1), dtype=torch.complex128, device="cuda")
+        with pytest.raises(chase.ChaseError) as ei:
+            srv.submit(dev_colmajor(synth.dk_matrix(4000, seed=1)), 200, 100)
+        assert ei.value.status == chase.CHASE_ENOMEM
+        del big
+
+
+def test_fill_callback_generates_h_at_admission():
+    torch_cuda()
+    N, nev, nex, seed = 2200, 12, 6, 21
+    lib = synth._slib()
+
+    def fill(ptr, n, ld, stream):
+        return lib.synth_dk(ctypes.c_void_p(ptr), ld, n, seed, 0.02, 200.0, 1.0, 6.0,
+                            ctypes.c_void_p(stream))
+
+    ref = _solo(synth.dk_matrix_device(N, seed=seed), nev, nex)
+    with chase.Server(slots=2) as srv:
+        t = srv.submit_fill(fill, N, nev, nex)
+        assert srv.wait(t, timeout=120.0)
+        out = srv.poll(t)
+    assert np.array_equal(ref.eigvals, out.eigvals)
+    assert np.array_equal(host(ref.V), host(out.V))
