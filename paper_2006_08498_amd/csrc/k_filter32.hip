@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_filter32_reduce(
 }
 
 constexpr int prefetch_depth32(int wn) {
-    return wn == 1 ? 8 : wn == 2 ? 6 : wn <= 4 ? 4 : wn <= 6 ? 3 : 2;
+    return wn <= 4 ? 8 : wn <= 6 ? 6 : 4;
 }
 
 template <int WN>
@@ -246,7 +246,7 @@ FilterPlan filter32_plan(int64_t N, int n) {
     }
     p.rb = (int)((N + 63) / 64);
     // Resident workgroups per CU from the FP32 kernels' register budgets.
-    static const int occ[11] = {0, 4, 4, 4, 3, 3, 2, 2, 2, 2, 1};
+    static const int occ[11] = {0, 4, 3, 2, 2, 2, 1, 2, 1, 1, 1};
     const int64_t slots = 256 * (int64_t)occ[p.wn];
     const int64_t units = (int64_t)p.rb * p.cb;
     double best = 1e300;
