@@ -113,6 +113,11 @@ typedef struct chase_info {
                                   of H (seconds) */
     double t_filter32_kernels; /* FP32 filter kernel durations (profile) */
     int64_t filter32_launches; /* FP32 filter kernel launches */
+    /* profile: every FP64 H-times-block kernel launch of the solve (filter,
+     * Lanczos and Rayleigh-Ritz): summed duration, algorithmic flops
+     * (8 N^2 per column) and launch count */
+    double gemm_time, gemm_flops;
+    int64_t gemm_launches;
 } chase_info;
 
 /* Fills *o with the defaults listed above. */

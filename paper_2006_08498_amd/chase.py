@@ -81,6 +81,9 @@ class ChaseInfo(ctypes.Structure):
         ("t_shadow", ctypes.c_double),
         ("t_filter32_kernels", ctypes.c_double),
         ("filter32_launches", ctypes.c_int64),
+        ("gemm_time", ctypes.c_double),
+        ("gemm_flops", ctypes.c_double),
+        ("gemm_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -329,7 +329,8 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     std::memset(&R.info, 0, sizeof(R.info));
     chase_info &info = R.info;
     Events E;
-    std::vector<hipEvent_t> prof, prof32;
+    std::vector<hipEvent_t> prof, prof32, profx;
+    std::vector<int> profx_cols;
     std::vector<hipEvent_t> *profp = o.profile ? &prof : nullptr;
     std::vector<hipEvent_t> *prof32p = o.profile ? &prof32 : nullptr;
 
@@ -357,6 +358,34 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         }
         for (auto e : prof32) (void)hipEventDestroy(e);
         prof32.clear();
+        for (size_t i = 0; i + 3 <= profx.size(); i += 3) {
+            info.gemm_time += elapsed(profx[i], profx[i + 1]);
+            info.gemm_flops += 8.0 * (double)N * (double)N * profx_cols[i / 3];
+            info.gemm_launches += 1;
+        }
+        for (auto e : profx) (void)hipEventDestroy(e);
+        profx.clear();
+        profx_cols.clear();
+    };
+    // H times a block outside the filter (Lanczos, Rayleigh-Ritz), timed in
+    // profile mode like the filter launches.
+    auto gemm_other = [&](const Z *Yb, int64_t ldy, Z *Wb, int64_t ldw, int cols) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (o.profile) {
+            CHASE_HIP(hipEventCreate(&e0));
+            CHASE_HIP(hipEventCreate(&e1));
+            CHASE_HIP(hipEventCreate(&e2));
+            CHASE_HIP(hipEventRecord(e0, s));
+        }
+        filter_gemm(p.H, p.ldh, N, Yb, ldy, nullptr, ldy, Wb, ldw, cols, 1.0, 0.0, 0.0,
+                    fpart, s, e1);
+        if (o.profile) {
+            CHASE_HIP(hipEventRecord(e2, s));
+            profx.push_back(e0);
+            profx.push_back(e1);
+            profx.push_back(e2);
+            profx_cols.push_back(cols);
+        }
     };
 
     // ---------------- Lanczos: spectral bounds (once per solve)
@@ -365,7 +394,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     random_block(Lw, r, N, r, o.seed, 1u, s);
     lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, 0, 1, s);
     for (int j = 0; j < k; ++j) {
-        filter_gemm(p.H, p.ldh, N, Lv, r, nullptr, r, Lw, r, r, 1.0, 0.0, 0.0, fpart, s);
+        gemm_other(Lv, r, Lw, r, r);
         lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, j, 0, s);
     }
     CHASE_HIP(hipEventRecord(l1, s));
@@ -436,7 +465,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
                   reinterpret_cast<int *>(h_misc), o.seed, qr_salt, s);
         CHASE_HIP(hipEventRecord(ev[2], s));
         Z *Q = V + L;
-        filter_gemm(p.H, p.ldh, N, Q, ne, nullptr, ne, W + L, ne, n, 1.0, 0.0, 0.0, fpart, s);
+        gemm_other(Q, ne, W + L, ne, n);
         gram(Q, ne, W + L, ne, N, n, n, G, n, gpart, s);
         hermitise(G, n, s);
         jacobi_eig(G, n, theta, Y, jwork, h_jac, s);
@@ -535,6 +564,12 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     phase_normalise_out(B1, nev, N, nev, dV, ldv, npart, s);
     CHASE_HIP(hipStreamSynchronize(s));
     info.filter_flops = 8.0 * (double)N * (double)N * (double)info.matvecs_filter;
+    if (o.profile) {
+        info.gemm_time += info.t_filter_kernels;
+        info.gemm_flops += 8.0 * (double)N * (double)N *
+                           (double)(info.matvecs_filter - info.matvecs_filter_fp32);
+        info.gemm_launches += info.filter_launches;
+    }
     info.matvecs_total += info.matvecs_filter;
     info.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return R;

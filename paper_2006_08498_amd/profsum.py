@@ -1,0 +1,162 @@
+"""Summaries of rocprofv3 CSV output for the filter kernels.
+
+    python -m paper_2006_08498_amd.profsum stats DIR [--match SUBSTR]
+    python -m paper_2006_08498_amd.profsum traffic --fetch D --write D \
+        --copy-fetch D --copy-write D --copy-bytes B [--match SUBSTR] [--workload W]
+
+`stats` prints the rows of the kernel-statistics CSV under DIR (from
+`rocprofv3 --kernel-trace --stats --output-format csv`) whose kernel name
+contains SUBSTR, plus their call-weighted average duration.
+
+`traffic` turns two counter runs (`--pmc FETCH_SIZE`, then `--pmc
+WRITE_SIZE`, KiB per dispatch) into HBM bytes per launch.  Each counter is
+scaled by the factor that maps what it reads for a plain device copy of B
+bytes (read B, write B) to B, so the figures are in true bytes whatever
+fraction of the memory channels the counter observes.  The last line is a
+JSON record, prefixed `traffic-record:`, that carries the digest of the
+kernel sources it was measured on; a benchmark reports the traffic only
+while the digest still matches.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+# Sources that define each filter kernel and its launch plan.
+KERNEL_SOURCES = {
+    "k_filter": ("k_filter_kern.h", "k_filter.hip", "k_filter_wide.hip", "common.h"),
+    "k_filter32": ("k_filter32.hip", "common.h"),
+}
+
+
+def sources_digest(kernel: str) -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _csvs(d, suffix):
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def kernel_stats(d, match):
+    rows = []
+    for f in _csvs(d, "kernel_stats.csv"):
+        for r in csv.DictReader(open(f)):
+            if match in r["Name"]:
+                rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]),
+                             float(r["TotalDurationNs"])))
+    return rows
+
+
+def counter_values(d, match, counter):
+    """Per-dispatch values of `counter` for kernels whose name contains match."""
+    per = collections.defaultdict(list)
+    for f in _csvs(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and match in r["Kernel_Name"]:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def _short(name):
+    # 'void ns::k_filter<9, 0, false>(args...)' -> 'k_filter<9, 0, false>'
+    head = name.split("(")[0]
+    return head.replace("void ", "").split("::")[-1]
+
+
+def cmd_stats(a):
+    rows = kernel_stats(a.dir, a.match)
+    calls = sum(r[1] for r in rows)
+    total = sum(r[3] for r in rows)
+    print("| kernel | calls | avg us | total ms |")
+    print("|---|---:|---:|---:|")
+    for name, c, avg, tot in sorted(rows, key=lambda r: -r[3]):
+        print(f"| {_short(name)} | {c} | {avg / 1e3:.2f} | {tot / 1e6:.2f} |")
+    if calls:
+        print(f"| all `{a.match}` | {calls} | {total / calls / 1e3:.2f} | {total / 1e6:.2f} |")
+
+
+def cmd_traffic(a):
+    cf = counter_values(a.copy_fetch, "copy", "FETCH_SIZE")
+    cw = counter_values(a.copy_write, "copy", "WRITE_SIZE")
+    cf_mean = sum(sum(v) for v in cf.values()) / max(1, sum(len(v) for v in cf.values()))
+    cw_mean = sum(sum(v) for v in cw.values()) / max(1, sum(len(v) for v in cw.values()))
+    if cf_mean <= 0 or cw_mean <= 0:
+        sys.exit("copy-kernel counters missing")
+    kf = a.copy_bytes / (cf_mean * 1024.0)
+    kw = a.copy_bytes / (cw_mean * 1024.0)
+    fv = counter_values(a.fetch, a.match, "FETCH_SIZE")
+    wv = counter_values(a.write, a.match, "WRITE_SIZE")
+    print(f"copy of {a.copy_bytes} bytes: FETCH_SIZE {cf_mean:.6g} KiB -> factor {kf:.4f}; "
+          f"WRITE_SIZE {cw_mean:.6g} KiB -> factor {kw:.4f}")
+    print()
+    print("| kernel | launches | read GB/launch | written MB/launch |")
+    print("|---|---:|---:|---:|")
+    nf = nw = 0
+    sf = sw = 0.0
+    for name in sorted(fv):
+        f = fv[name]
+        w = wv.get(name, [])
+        nf += len(f)
+        nw += len(w)
+        sf += sum(f)
+        sw += sum(w)
+        rd = kf * 1024.0 * sum(f) / len(f)
+        wr = kw * 1024.0 * sum(w) / max(1, len(w))
+        print(f"| {_short(name)} | {len(f)} | {rd / 1e9:.3f} | {wr / 1e6:.2f} |")
+    if nf == 0 or nw == 0:
+        sys.exit("kernel counters missing")
+    rd = kf * 1024.0 * sf / nf
+    wr = kw * 1024.0 * sw / nw
+    print(f"| all | {nf} | {rd / 1e9:.3f} | {wr / 1e6:.2f} |")
+    print()
+    kern = "k_filter32" if "k_filter32" in a.match else "k_filter"
+    rec = {"kernel": kern, "workload": a.workload, "sources_digest": sources_digest(kern),
+           "launches": nf, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+           "bytes_per_launch": rd + wr, "fetch_factor": kf, "write_factor": kw}
+    print("traffic-record: " + json.dumps(rec))
+
+
+def read_record(path):
+    """The traffic record of a committed profile summary, or None."""
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    return json.loads(line.split(":", 1)[1])
+    except OSError:
+        return None
+    return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--match", default="k_filter<")
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--match", default="k_filter<")
+    t.add_argument("--workload", default="planted24k")
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()
