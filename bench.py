@@ -36,6 +36,9 @@ WORKLOADS = {
     # Mixed precision: FP32-MFMA filter switching to FP64, against plain FP64.
     "dk60k": dict(kind="dk", N=60000, nev=200, nex=60, degree_max=20, tol=1e-10,
                   std=0.01, decay=1000.0, precision="mixed"),
+    # Large: 160 GB of H generated on the device, mixed against plain FP64.
+    "dk100k": dict(kind="dk", N=100000, nev=300, nex=100, degree_max=30, tol=1e-10,
+                   std=0.02, decay=2000.0, precision="mixed"),
 }
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA (published)
 
@@ -234,6 +237,14 @@ def run_solves(H, w, ws, precision, steps, warmup, seed):
     from paper_2006_08498_amd import chase
     N, nev, nex = w["N"], w["nev"], w["nex"]
     opts = dict(profile=1, seed=seed, precision=precision)
+    if N >= 50000:
+        # Long solves report each iteration as it ends.
+        def progress(info):
+            log(f"  iteration {info['iterations']}: {info['nconv']}/{nev} locked, "
+                f"{info['matvecs_filter']} filter mat-vecs "
+                f"({info['matvecs_filter_fp32']} FP32), filter {info['t_filter']:.1f} s")
+            return False
+        opts["on_iteration"] = progress
     for i in range(warmup):
         r = chase.solve(H, nev, nex, w["tol"], w["degree_max"], workspace=ws, **opts)
         log(f"warmup {i}: {r.info['t_total']:.3f} s, {r.info['iterations']} iterations")
@@ -398,8 +409,10 @@ def main():
         # Plain FP64 at the same tolerance on the same matrix: the speedup
         # of the mixed form at equal accuracy.
         o64 = chase.default_opts()
-        ws = torch.empty(max(ws.numel(), chase.workspace_bytes(N, nev, nex, o64)),
-                         dtype=torch.uint8, device="cuda")
+        del ws                       # the mixed workspace holds H's FP32 copy
+        torch.cuda.empty_cache()
+        ws = torch.empty(chase.workspace_bytes(N, nev, nex, o64), dtype=torch.uint8,
+                         device="cuda")
         infos64, per64, r64 = run_solves(H, w, ws, chase.CHASE_FP64, max(1, args.steps // 2),
                                          min(args.warmup, 1), args.seed)
         chk64 = check_result(H, r64, lam, w["tol"])

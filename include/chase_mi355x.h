@@ -71,6 +71,9 @@ enum chase_precision {
                               above switch_tol, FP64 afterwards */
 };
 
+struct chase_info;
+typedef int (*chase_iter_fn)(void *user, const struct chase_info *info);
+
 typedef struct chase_opts {
     int32_t precision;        /* chase_precision; default CHASE_FP64 */
     int32_t max_iter;         /* subspace iterations; default 100 */
@@ -88,7 +91,16 @@ typedef struct chase_opts {
                                  random start */
     int32_t profile;          /* 1: time every filter launch with HIP events
                                  (fills t_filter_kernels) */
-    int32_t reserved[7];
+    int32_t reserved0;
+    /* Optional, called on the host thread running the solve (a server's
+     * worker thread for served requests) after every subspace iteration with the record so far (iterations, nconv = locked pairs,
+     * counters and phase times; alpha/mu1 of that iteration).  A nonzero
+     * return stops the solve after that iteration: the call then returns
+     * CHASE_ENOCONV (unless nev pairs are already locked) with the best
+     * pairs so far.  NULL = no callback. */
+    chase_iter_fn on_iteration;
+    void *on_iteration_user;
+    int32_t reserved[2];
 } chase_opts;
 
 typedef struct chase_info {

@@ -53,7 +53,10 @@ class ChaseOpts(ctypes.Structure):
         ("switch_tol", ctypes.c_double),
         ("dV0", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("reserved0", ctypes.c_int32),
+        ("on_iteration", ctypes.c_void_p),
+        ("on_iteration_user", ctypes.c_void_p),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -213,16 +216,31 @@ def workspace_bytes(N, nev, nex, opts=None) -> int:
     return int(lib().chase_workspace_bytes(N, nev, nex, ctypes.byref(o)))
 
 
+ITER_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ChaseInfo))
+
+
 def solve(H, nev, nex, tol=1e-10, degree_max=20, *, opts=None, V0=None,
-          workspace=None, stream=None, allow_noconv=False, **opt_kw):
+          workspace=None, stream=None, allow_noconv=False, on_iteration=None, **opt_kw):
     """Lowest ``nev`` eigenpairs of the Hermitian CUDA tensor ``H``.
 
     Returns eigenvalues (ascending), eigenvectors as an (N, nev) tensor,
-    residual norms, the status and the solver's info record."""
+    residual norms, the status and the solver's info record.
+    ``on_iteration(info_dict)`` is called after every subspace iteration; a
+    true return value stops the solve there (status CHASE_ENOCONV unless nev
+    pairs are locked)."""
     torch = _torch()
     N = H.shape[0]
     hp, ldh, conj = _h_layout(H)
     o = opts if opts is not None else default_opts(**opt_kw)
+    cb_keep = None
+    if on_iteration is not None:
+        def _cb(_user, info_p):
+            try:
+                return 1 if on_iteration(info_p.contents.as_dict()) else 0
+            except Exception:               # never unwind through C
+                return 1
+        cb_keep = ITER_FN(_cb)
+        o.on_iteration = ctypes.cast(cb_keep, ctypes.c_void_p)
     v0_keep = None
     if V0 is not None:
         # Warm start, N x (nev+nex): the ABI wants it column-major (and
@@ -241,6 +259,7 @@ def solve(H, nev, nex, tol=1e-10, degree_max=20, *, opts=None, V0=None,
         hp, N, ldh, nev, nex, tol, degree_max,
         ev.ctypes.data_as(_P), rs.ctypes.data_as(_P), _dptr(out), N,
         wptr, wbytes, _stream_ptr(stream), ctypes.byref(o), ctypes.byref(info))
+    del cb_keep
     _check(st, (CHASE_OK, CHASE_ENOCONV) if allow_noconv else (CHASE_OK,))
     V = out.t()
     if conj:

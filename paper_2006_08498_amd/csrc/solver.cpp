@@ -496,7 +496,11 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         while (cnt < n && res[L + cnt] <= tol_abs) ++cnt;
         L += cnt;
         info.iterations = it;
-        if (L >= nev || it == o.max_iter) break;
+        info.nconv = std::min(L, nev);
+        info.alpha = alpha;
+        info.mu1 = mu1;
+        const bool stop = o.on_iteration && o.on_iteration(o.on_iteration_user, &info) != 0;
+        if (L >= nev || it == o.max_iter || stop) break;
         // Filter interval, rates and degrees for the next iteration.  The
         // per-vector state is kept in Ritz order (position j = j-th smallest
         // Ritz value of the active block, as Rayleigh-Ritz returns it); only

@@ -127,6 +127,26 @@ def dk_entries(i, j, seed, std, decay):
     return np.where(i == j, diag, off)
 
 
+def dk_rows(rows, N, seed=0, std=0.02, decay=200.0):
+    """Selected full rows H[rows, :] of D + K (same entries as dk_matrix),
+    without forming the matrix."""
+    rows = np.asarray(rows, dtype=np.int64)
+    d = dk_diag(N, seed)
+    out = np.empty((rows.size, N), dtype=np.complex128)
+    j = np.arange(N, dtype=np.int64)
+    for t, i in enumerate(rows):
+        lo = j <= i
+        ii = np.full(N, i, dtype=np.int64)
+        # lower part (j <= i) is generated at (i, j); upper part is the
+        # conjugate of the entry generated at (j, i)
+        low = dk_entries(ii[lo], j[lo], seed, std, decay)
+        up = np.conj(dk_entries(j[~lo], ii[~lo], seed, std, decay))
+        out[t, lo] = low
+        out[t, ~lo] = up
+        out[t, i] = np.real(low[i]) + d[i]
+    return out
+
+
 def dk_matrix(N, seed=0, std=0.02, decay=200.0, row_block=512):
     """Dense D + K (complex128, Hermitian to the last bit)."""
     H = np.zeros((N, N), dtype=np.complex128)

@@ -1,9 +1,13 @@
-"""Full-size parity for the benchmark workload (GPU).
+"""Full-size parity for the benchmark workloads (GPU).
 
-N = 24000 planted spectrum, nev = 100, nex = 40, degree <= 20, tol = 1e-10,
-in the launch configuration bench.py times.  The oracle's O(N^3) solve is
-out of reach at this size; the planted eigenvalues are the exact outputs,
-and residual / orthogonality are properties that hold at any size.
+* N = 24000 planted spectrum, nev = 100, nex = 40, degree <= 20, tol = 1e-10,
+  in the launch configuration bench.py times.  The planted eigenvalues are
+  the exact outputs.
+* N = 60000 D + K (std 0.01, decay 1000), nev = 200, nex = 60, mixed
+  precision.  The oracle's O(N^3) solve is out of reach; the host
+  regenerates sampled rows of H from the generator's definition and checks
+  every returned pair on them, and residual, orthogonality and Weyl's bound
+  (|lambda_i - sort(d)_i| <= ||K||_2) hold at any size.
 """
 import numpy as np
 import pytest
@@ -32,3 +36,40 @@ def test_planted_24000_full_size():
     assert float((G - I).abs().max()) <= 1e-12
     # The library's own residuals agree with the independent check.
     assert np.allclose(r.resid / lam.max(), res, rtol=1e-3, atol=1e-14)
+
+
+def test_mixed_60000_full_size():
+    torch = torch_cuda()
+    N, nev, nex, seed, std, decay = 60000, 200, 60, 0, 0.01, 1000.0
+    H = synth.dk_matrix_device(N, seed=seed, std=std, decay=decay)
+    o = chase.default_opts(precision=chase.CHASE_MIXED)
+    ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8,
+                     device="cuda")
+    r = chase.solve(H, nev, nex, 1e-10, 20, workspace=ws, precision=chase.CHASE_MIXED)
+    del ws
+    assert r.status == chase.CHASE_OK
+    assert r.info["matvecs_filter_fp32"] > 0
+    lam = r.eigvals
+    assert np.all(np.diff(lam) >= 0)
+    hn = r.info["hnorm_est"]                 # a lower estimate of ||H||_2
+    V = r.V
+    w = torch.as_tensor(lam, device="cuda")
+    res = torch.linalg.vector_norm(H @ V - V * w[None, :], dim=0).cpu().numpy() / hn
+    assert res.max() <= 1e-10
+    G = V.conj().t() @ V
+    assert float((G - torch.eye(nev, dtype=G.dtype, device="cuda")).abs().max()) <= 1e-12
+    # Weyl: K = H - D, ||K||_2 <= max row sum of |K| (H is Hermitian).
+    d = synth.dk_diag(N, seed)
+    dg = H.diagonal().real.cpu().numpy()
+    rowsum = H.abs().sum(dim=0).cpu().numpy() - np.abs(dg) + np.abs(dg - d)
+    assert np.all(np.abs(lam - np.sort(d)[:nev]) <= rowsum.max())
+    # Sampled rows of H regenerated on the host: (H v)_i - lambda v_i for
+    # every returned pair, in FP64 on the host.
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(N, 24, replace=False))
+    Hr = synth.dk_rows(rows, N, seed, std, decay)
+    Vh = V.cpu().numpy()
+    R = Hr @ Vh - Vh[rows] * lam[None, :]
+    eps = np.finfo(np.float64).eps
+    bound = 1e-10 * hn + 2 * N * eps * (np.abs(Hr) @ np.abs(Vh))
+    assert np.all(np.abs(R) <= bound)

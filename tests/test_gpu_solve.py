@@ -162,3 +162,30 @@ def test_caller_workspace_and_profile_counters():
     _check_against_oracle(H, r, 10)
     assert r.info["filter_launches"] > 0 and r.info["t_filter_kernels"] > 0
     assert r.info["filter_flops"] == 8.0 * 1000 * 1000 * r.info["matvecs_filter"]
+    # Every FP64 H-times-block launch is timed: filter steps plus the
+    # Lanczos products plus one Rayleigh-Ritz product per iteration.
+    lz = chase.default_opts()
+    assert r.info["gemm_launches"] == (r.info["filter_launches"] + lz.lanczos_steps
+                                       + r.info["iterations"])
+    assert r.info["gemm_flops"] == 8.0 * 1000 * 1000 * r.info["matvecs_total"]
+    assert r.info["gemm_time"] >= r.info["t_filter_kernels"] > 0
+
+
+def test_iteration_callback_reports_and_stops():
+    torch_cuda()
+    H = synth.dk_matrix(1200, seed=9)
+    dH = dev_colmajor(H)
+    seen = []
+    full = chase.solve(dH, 12, 6, on_iteration=lambda i: seen.append(dict(i)) and False)
+    assert [s["iterations"] for s in seen] == list(range(1, full.info["iterations"] + 1))
+    assert all(a["nconv"] <= b["nconv"] for a, b in zip(seen, seen[1:]))
+    assert seen[-1]["nconv"] == 12
+    # Same pairs as without a callback (the callback only observes).
+    plain = chase.solve(dH, 12, 6)
+    assert np.array_equal(plain.eigvals, full.eigvals)
+    # A true return stops after that iteration with the best pairs so far.
+    stop = chase.solve(dH, 12, 6, on_iteration=lambda i: i["iterations"] >= 2,
+                       allow_noconv=True)
+    assert stop.info["iterations"] == 2
+    assert stop.status == (chase.CHASE_OK if seen[1]["nconv"] >= 12 else chase.CHASE_ENOCONV)
+    assert stop.info["nconv"] == seen[1]["nconv"]
