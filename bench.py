@@ -230,13 +230,15 @@ def cpu_baseline(w, seed, budget_s):
                       f"family took {t:.2f} s; scaled by (N/{ns2})^3 to N={N}"}
 
 
-def run_solves(H, w, ws, precision, steps, warmup, seed):
+def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None):
     """warmup untimed solves, then `steps` timed solves (the library call is
     synchronous); returns the info records, seconds per solve, last result."""
     import torch
     from paper_2006_08498_amd import chase
     N, nev, nex = w["N"], w["nev"], w["nex"]
     opts = dict(profile=1, seed=seed, precision=precision)
+    if switch_tol is not None:
+        opts["switch_tol"] = switch_tol
     if N >= 50000:
         # Long solves report each iteration as it ends.
         def progress(info):
@@ -277,6 +279,9 @@ def main():
     ap.add_argument("--h-cache", default="",
                     help="file holding the generated matrix: written if absent, "
                          "read if present (keeps matrix generation out of profiled runs)")
+    ap.add_argument("--switch-tol", type=float, default=None,
+                    help="mixed workloads: residual / ||H|| above which a vector is "
+                         "filtered in FP32 (library default if omitted)")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="mixed workloads: skip timing the plain FP64 solve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -331,7 +336,8 @@ def main():
     precision = chase.CHASE_MIXED if w["precision"] == "mixed" else chase.CHASE_FP64
     o = chase.default_opts(precision=precision)
     ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8, device="cuda")
-    infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed)
+    infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed,
+                               args.switch_tol)
     chk = check_result(H, r, lam, w["tol"])
     log(f"check: {chk}")
 
@@ -394,7 +400,10 @@ def main():
                                f"degree<={w['degree_max']} tol={w['tol']} "
                                f"precision={w['precision']}",
                    "N": N, "nev": nev, "nex": nex, "degree_max": w["degree_max"],
-                   "tol": w["tol"], "precision": w["precision"], "parallelism": "1 GPU"},
+                   "tol": w["tol"], "precision": w["precision"], "parallelism": "1 GPU",
+                   **({"switch_tol": args.switch_tol if args.switch_tol is not None
+                       else chase.default_opts().switch_tol}
+                      if precision == chase.CHASE_MIXED else {})},
         "filter_tflops": S["filter_flops"] / S["t_filter"] / 1e12 if S["t_filter"] > 0 else 0.0,
         "filter_kernel_tflops_fp64": ach64,
         "filter_kernel_tflops_fp32": ach32,

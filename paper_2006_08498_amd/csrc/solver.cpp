@@ -513,8 +513,11 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
             if (Lo.mixed) {
                 // FP32 has stalled on this vector if its residual fell by
                 // less than a quarter of the orders of magnitude the filter
-                // rate predicted (rho^m); it is then filtered in FP64.
-                if (fp32[j] && std::isfinite(res_prev[j]) && pred_gain[j] >= 100.0 &&
+                // rate predicted (rho^m); it is then filtered in FP64.  Any
+                // prediction above 10% counts: near the FP32 floor the
+                // target is close, the degree short and rho^m small, and a
+                // vector stuck there must still be caught.
+                if (fp32[j] && std::isfinite(res_prev[j]) && pred_gain[j] >= 1.1 &&
                     res_prev[j] / res[j] < std::pow(pred_gain[j], 0.25))
                     use64[j] = 1;
                 res_prev[j] = res[j];

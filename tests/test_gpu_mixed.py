@@ -83,3 +83,16 @@ def test_mixed_switch_tolerance_extremes():
     b = chase.solve(dH, 10, 6, 1e-10, 20, precision=chase.CHASE_MIXED, switch_tol=1e-14)
     _check(H, b, 10)
     assert b.info["matvecs_filter_fp32"] >= a.info["matvecs_filter_fp32"]
+
+
+@pytest.mark.parametrize("switch_tol", [1e-7, 1e-9])
+def test_mixed_switch_below_fp32_floor_still_converges(switch_tol):
+    """A switch level at or below what FP32 filtering can reach: vectors
+    that stall there must move to FP64 and the solve must still converge."""
+    torch_cuda()
+    H = synth.dk_matrix(4000, seed=2, std=0.01, decay=1000.0)
+    r = chase.solve(dev_colmajor(H), 40, 16, 1e-10, 20, precision=chase.CHASE_MIXED,
+                    switch_tol=switch_tol)
+    assert r.status == chase.CHASE_OK
+    assert r.info["matvecs_filter_fp32"] > 0
+    _check(H, r, 40)
