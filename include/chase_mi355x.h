@@ -85,7 +85,8 @@ typedef struct chase_opts {
     int32_t lanczos_runs;     /* independent Lanczos runs; default 4 */
     uint64_t seed;            /* start vectors (Philox4x32-10); default 0 */
     double switch_tol;        /* CHASE_MIXED: residual / ||H|| above which a
-                                 vector is filtered in FP32; default 1e-5 */
+                                 vector is filtered in FP32 (until FP32 stalls on
+                                 it); default 1e-7, about the FP32 floor */
     const chase_z *dV0;       /* optional warm start, N x (nev+nex),
                                  column-major, leading dimension N; NULL =
                                  random start */

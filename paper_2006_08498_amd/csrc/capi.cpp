@@ -114,7 +114,7 @@ void chase_default_opts(chase_opts *o) {
     o->lanczos_steps = 25;
     o->lanczos_runs = 4;
     o->seed = 0;
-    o->switch_tol = 1e-5;
+    o->switch_tol = 1e-7;
     o->dV0 = nullptr;
     o->profile = 0;
 }

@@ -513,12 +513,15 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
             if (Lo.mixed) {
                 // FP32 has stalled on this vector if its residual fell by
                 // less than a quarter of the orders of magnitude the filter
-                // rate predicted (rho^m); it is then filtered in FP64.  Any
-                // prediction above 10% counts: near the FP32 floor the
-                // target is close, the degree short and rho^m small, and a
-                // vector stuck there must still be caught.
+                // rate predicted (rho^m), and by less than 8x; it is then
+                // filtered in FP64.  Any prediction above 10% counts: near
+                // the FP32 floor the target is close, the degree short and
+                // rho^m small, and a vector stuck there must still be
+                // caught.  The 8x cap keeps the early iterations, whose
+                // Ritz values (and so predicted rates) are still rough, from
+                // reading a 60x gain against a predicted 1e9 as a stall.
                 if (fp32[j] && std::isfinite(res_prev[j]) && pred_gain[j] >= 1.1 &&
-                    res_prev[j] / res[j] < std::pow(pred_gain[j], 0.25))
+                    res_prev[j] / res[j] < std::min(std::pow(pred_gain[j], 0.25), 8.0))
                     use64[j] = 1;
                 res_prev[j] = res[j];
                 fp32[j] = (!use64[j] && res[j] > sw_abs) ? 1 : 0;
