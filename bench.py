@@ -80,7 +80,7 @@ def run_serve(args):
                                  cfg["decay"], 1.0, 6.0, ctypes.c_void_p(stream))
         return fill
 
-    srv = chase.Server(budget_bytes=0, slots=args.slots)
+    srv = chase.Server(budget_bytes=0, slots=args.slots, fuse=args.fuse)
     log(f"serving {len(sched)} requests over {sched[-1]['t']:.1f} s with "
         f"{args.slots} slots")
     pending = {}
@@ -137,7 +137,8 @@ def run_serve(args):
         "data": "synthetic",
         "config": {"workload": "serve128: 128 requests, Poisson 4/s, N in {4k..20k} D+K, "
                                "nev in [30,150], nex=0.4 nev, tol 1e-10, degree<=20",
-                   "slots": args.slots, "parallelism": "1 GPU"},
+                   "slots": args.slots, "fuse_filter": bool(args.fuse),
+                   "parallelism": "1 GPU"},
         "p50_s": p50, "p99_s": p99,
         "throughput_req_per_s": n / makespan,
         "makespan_s": makespan,
@@ -145,6 +146,7 @@ def run_serve(args):
         "mean_queue_s": float(np.mean([r.queued_s for _, r, _ in done])),
         "mean_gpu_s": float(np.mean([r.gpu_s for _, r, _ in done])),
         "peak_running": peak["peak_running"], "peak_bytes": peak["peak_bytes"],
+        "fused_ticks": peak["fused_ticks"], "fused_steps": peak["fused_steps"],
         "check": {"max_resid_rel_sampled": worst},
     }
     if args.serve_solo_baseline:
@@ -271,6 +273,8 @@ def main():
     ap.add_argument("--workload", default="planted24k",
                     choices=sorted(WORKLOADS) + ["serve128"])
     ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
+    ap.add_argument("--fuse", type=int, default=0,
+                    help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
     ap.add_argument("--serve-solo-baseline", action="store_true",
                     help="serve128: also time every request alone, one after another")
     ap.add_argument("--seed", type=int, default=0)

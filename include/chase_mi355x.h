@@ -193,6 +193,31 @@ int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
                       chase_z *dW, int64_t ldw, int32_t ncols,
                       double a, double b, double g, void *stream);
 
+/* One filter step of a grouped launch: the arguments of chase_filter_step. */
+typedef struct chase_filter_call {
+    const chase_z *dH;
+    int64_t N, ldh;
+    const chase_z *dY;
+    int64_t ldy;
+    const chase_z *dX;
+    int64_t ldx;
+    chase_z *dW;
+    int64_t ldw;
+    int32_t ncols;
+    double a, b, g;
+} chase_filter_call;
+
+/*
+ * Several independent filter steps (different H, N and blocks; each with
+ * chase_filter_step's contract and checks) in grouped launches: one MFMA
+ * grid per distinct tile width holding every step's tiles, then one grid
+ * for the split-K reductions.  This is how the server fuses the filter
+ * steps of concurrent solves.  Each step's result is bitwise the one
+ * chase_filter_step gives.  count in [0, 1024]; the W blocks must not
+ * overlap one another or any Y.
+ */
+int chase_filter_step_group(const chase_filter_call *calls, int32_t count, void *stream);
+
 /*
  * Mixed-precision form (filter with vectors above the switch tolerance):
  * the same step in FP32 on the complex64 copy Hc of H (column-major, ldh)
@@ -308,10 +333,20 @@ typedef struct chase_server chase_server;
 typedef int (*chase_fill_fn)(chase_z *dH, int64_t N, int64_t ldh, void *user,
                              void *stream);
 
+/* Server flags. */
+enum {
+    /* Fuse the FP64 filter steps of concurrent solves: one grouped launch
+     * per tick holds the next step of every running solve that is in its
+     * filter phase (chase_filter_step_group), instead of one launch per
+     * step per solve.  Results are bitwise the same either way. */
+    CHASE_SERVER_FUSE_FILTER = 1
+};
+
 /* hbm_budget_bytes: device memory the server may allocate (0 = free memory
- * minus a reserve); max_slots: concurrent solves (1..64).  NULL on failure
- * (chase_server_last_error()). */
-chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots);
+ * minus a reserve); max_slots: concurrent solves (1..64); flags: 0 or
+ * CHASE_SERVER_FUSE_FILTER.  NULL on failure (chase_server_last_error()). */
+chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots,
+                                  uint32_t flags);
 
 /* Queues a request.  H is a host matrix (copied now, uploaded at admission,
  * counted in the footprint) when is_device == 0, else a caller-owned device
@@ -349,6 +384,10 @@ int chase_server_wait(chase_server *srv, uint64_t ticket, double timeout_s);
 int chase_server_stats(chase_server *srv, size_t *bytes_in_use,
                        size_t *peak_bytes, int32_t *running,
                        int32_t *peak_running, int32_t *queued);
+
+/* With CHASE_SERVER_FUSE_FILTER: grouped launches issued so far (ticks)
+ * and the filter steps they held; both 0 without fusion. */
+int chase_server_fusion_stats(chase_server *srv, int64_t *ticks, int64_t *steps);
 
 /* Message for the last server call that failed on this thread. */
 const char *chase_server_last_error(void);

@@ -31,6 +31,7 @@ CHASE_EBOUNDS = 6
 CHASE_EINTERNAL = 7
 CHASE_FP64 = 0
 CHASE_MIXED = 1
+CHASE_SERVER_FUSE_FILTER = 1
 
 STATUS_NAMES = {
     CHASE_PENDING: "CHASE_PENDING", CHASE_OK: "CHASE_OK",
@@ -114,6 +115,7 @@ SIGNATURES = {
                                       ctypes.POINTER(ChaseOpts), ctypes.POINTER(ChaseInfo)]),
     "chase_filter_step": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
                                          _I32, _D, _D, _D, _P]),
+    "chase_filter_step_group": (ctypes.c_int, [_P, _I32, _P]),
     "chase_filter_step_c": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
                                            _I32, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, _P]),
@@ -317,6 +319,30 @@ def shadow_c(H, stream=None):
     return Hc
 
 
+class FilterCall(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_void_p), ("N", ctypes.c_int64), ("ldh", ctypes.c_int64),
+                ("dY", ctypes.c_void_p), ("ldy", ctypes.c_int64),
+                ("dX", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("dW", ctypes.c_void_p), ("ldw", ctypes.c_int64), ("ncols", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+def filter_step_group(steps, stream=None):
+    """Several filter steps in grouped launches.  ``steps`` is a list of
+    (H, Y, X, W, a, b, g) with the shapes of filter_step (X may be None when
+    g == 0; W must be given)."""
+    arr = (FilterCall * max(1, len(steps)))()
+    for i, (H, Y, X, W, a, b, g) in enumerate(steps):
+        hp, ldh = _h_colmajor(H)
+        N, n = Y.shape
+        yp, ldy = _block(Y, "Y")
+        xp, ldx = _block(X, "X") if X is not None else (None, n)
+        wp, ldw = _block(W, "W")
+        arr[i] = FilterCall(hp, N, ldh, yp, ldy, xp, ldx, wp, ldw, n, a, b, g)
+    _check(lib().chase_filter_step_group(ctypes.cast(arr, _P), len(steps),
+                                         _stream_ptr(stream)))
+
+
 def filter_step_c(Hc, Y, X, a, b, g, W=None, stream=None):
     """FP32 step W = a Hc Y + b Y + g X on complex64 blocks."""
     torch = _torch()
@@ -426,7 +452,9 @@ FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes
                            ctypes.c_void_p, ctypes.c_void_p)
 
 SIGNATURES.update({
-    "chase_server_create": (ctypes.c_void_p, [ctypes.c_size_t, _I32]),
+    "chase_server_create": (ctypes.c_void_p, [ctypes.c_size_t, _I32, ctypes.c_uint32]),
+    "chase_server_fusion_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.POINTER(ctypes.c_int64)]),
     "chase_server_submit": (ctypes.c_int, [_P, _P, ctypes.c_int, _I64, _I64, _I32, _I32, _D,
                                            _I32, ctypes.POINTER(ChaseOpts),
                                            ctypes.POINTER(ctypes.c_uint64)]),
@@ -466,9 +494,10 @@ class Server:
     callable fill(ptr, N, ld, stream_ptr) -> int run at admission on the
     slot's stream."""
 
-    def __init__(self, budget_bytes=0, slots=4):
+    def __init__(self, budget_bytes=0, slots=4, fuse=False):
         L = lib()
-        self._s = L.chase_server_create(int(budget_bytes), int(slots))
+        self._s = L.chase_server_create(int(budget_bytes), int(slots),
+                                        CHASE_SERVER_FUSE_FILTER if fuse else 0)
         if not self._s:
             msg = L.chase_server_last_error()
             raise ChaseError(CHASE_EINTERNAL, msg.decode() if msg else "create failed")
@@ -539,8 +568,11 @@ class Server:
         c, d, e = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         lib().chase_server_stats(self._s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                  ctypes.byref(d), ctypes.byref(e))
+        t, k = ctypes.c_int64(0), ctypes.c_int64(0)
+        lib().chase_server_fusion_stats(self._s, ctypes.byref(t), ctypes.byref(k))
         return {"bytes_in_use": a.value, "peak_bytes": b.value, "running": c.value,
-                "peak_running": d.value, "queued": e.value}
+                "peak_running": d.value, "queued": e.value, "fused_ticks": t.value,
+                "fused_steps": k.value}
 
     def close(self):
         if self._s:

@@ -201,6 +201,41 @@ int chase_filter_step(const chase_z *dH, int64_t N, int64_t ldh,
     });
 }
 
+int chase_filter_step_group(const chase_filter_call *calls, int32_t count, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(count >= 0 && count <= 1024, "count must be in [0, 1024]");
+        REQUIRE(count == 0 || calls, "calls is NULL");
+        size_t elems = 0;
+        for (int i = 0; i < count; ++i) {
+            const chase_filter_call &c = calls[i];
+            REQUIRE(c.N >= 1 && c.N <= (int64_t)1 << 31, "bad N");
+            REQUIRE(c.ncols >= 0, "ncols must be >= 0");
+            REQUIRE(c.dH && c.dY && c.dW, "NULL pointer");
+            REQUIRE(c.g == 0.0 || c.dX, "dX is NULL while g != 0");
+            REQUIRE(c.ldh >= c.N && c.ldy >= c.ncols && c.ldw >= c.ncols &&
+                        (!c.dX || c.ldx >= c.ncols),
+                    "bad leading dimension");
+            elems += filter_partial_elems(c.N, c.ncols);
+        }
+        hipStream_t s = S(stream);
+        DevBuf part(elems * sizeof(Z), s);
+        std::vector<FilterCall> fc;
+        size_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            const chase_filter_call &c = calls[i];
+            fc.push_back(FilterCall{reinterpret_cast<const Z *>(c.dH), c.ldh, c.N,
+                                    reinterpret_cast<const Z *>(c.dY), c.ldy,
+                                    reinterpret_cast<const Z *>(c.dX), c.ldx,
+                                    reinterpret_cast<Z *>(c.dW), c.ldw, c.ncols, c.a, c.b,
+                                    c.g, part.as<Z>() + off});
+            off += filter_partial_elems(c.N, c.ncols);
+        }
+        filter_gemm_group(fc.data(), count, s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
 int chase_filter_step_c(const chase_c *dHc, int64_t N, int64_t ldh,
                         const chase_c *dY, int64_t ldy, const chase_c *dX,
                         int64_t ldx, chase_c *dW, int64_t ldw, int32_t ncols,

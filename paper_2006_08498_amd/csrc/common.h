@@ -53,6 +53,27 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N, const Z *Y, int64_t ldy,
                  double b, double g, Z *part, hipStream_t s,
                  hipEvent_t after_mfma = nullptr);
 
+// One filter GEMM of a grouped launch (the same contract as filter_gemm).
+struct FilterCall {
+    const Z *H;
+    int64_t ldh, N;
+    const Z *Y;
+    int64_t ldy;
+    const Z *X;
+    int64_t ldx;
+    Z *W;
+    int64_t ldw;
+    int n;
+    double a, b, g;
+    Z *part;
+};
+// Several independent filter GEMMs (different H, sizes and buffers) in as
+// few launches as possible: one MFMA launch per distinct tile width and one
+// reduction launch for the split ones.  Each call keeps the tile plan
+// filter_plan(N, n) it would have alone, so its result is bitwise the same
+// as a filter_gemm call.
+void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s);
+
 // FP32 filter GEMM on the complex64 shadow Hc (mixed precision), same
 // contract as filter_gemm; partials: filter32_partial_elems(N, n) complex64.
 FilterPlan filter32_plan(int64_t N, int n);

@@ -25,12 +25,17 @@
 
 #include "k_filter_kern.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace chase {
 
 void launch_filter_wide(const FilterPlan &p, const Z *H, int64_t ldh, int N,
                         const Z *Y, int64_t ldy, const Z *X, int64_t ldx, Z *W,
                         int64_t ldw, int n, double a, double b, double g, Z *part,
                         hipStream_t s);
+void launch_filter_group_wide(int wn, const FilterPlan *plans, const FilterCall *calls,
+                              int count, hipStream_t s);
 
 namespace {
 using namespace filter_detail;
@@ -52,16 +57,43 @@ __global__ __launch_bounds__(256) void k_filter_reduce(
             si += p.y;
         }
         const Z yv = Y[row * ldy + col];
-        Z o;
-        o.x = a * sr + b * yv.x;
-        o.y = a * si + b * yv.y;
-        if (g != 0.0) {
-            const Z xv = X[row * ldx + col];
-            o.x += g * xv.x;
-            o.y += g * xv.y;
-        }
-        W[row * ldw + col] = o;
+        const Z xv = g != 0.0 ? X[row * ldx + col] : Z{0.0, 0.0};
+        W[row * ldw + col] = filter_epilogue(sr, si, yv, xv, a, b, g);
     }
+}
+
+// The reductions of several split GEMMs in one grid: GEMM i owns blocks
+// [start[i], start[i+1]) and strides over its own N*n entries.
+struct ReduceGroupArgs {
+    int count;
+    int start[kMaxGroup + 1];
+    FilterArgs p[kMaxGroup];
+};
+
+__global__ __launch_bounds__(256) void k_filter_reduce_group(const ReduceGroupArgs G) {
+    int i = 0;
+    while (i + 1 < G.count && (int)blockIdx.x >= G.start[i + 1]) ++i;
+    const FilterArgs &A = G.p[i];
+    const int nblk = G.start[i + 1] - G.start[i];
+    const int64_t total = (int64_t)A.N * A.n;
+    for (int64_t t = (blockIdx.x - G.start[i]) * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)nblk * blockDim.x) {
+        const int64_t row = t / A.n;
+        const int col = (int)(t - row * A.n);
+        double sr = 0.0, si = 0.0;
+        for (int s = 0; s < A.splits; ++s) {
+            const Z p = A.part[(int64_t)s * total + t];
+            sr += p.x;
+            si += p.y;
+        }
+        const Z yv = A.Y[row * A.ldy + col];
+        const Z xv = A.g != 0.0 ? A.X[row * A.ldx + col] : Z{0.0, 0.0};
+        A.W[row * A.ldw + col] = filter_epilogue(sr, si, yv, xv, A.a, A.b, A.g);
+    }
+}
+
+int reduce_blocks(int64_t N, int n) {
+    return (int)std::min<int64_t>(((int64_t)N * n + 255) / 256, 4096);
 }
 
 }  // namespace
@@ -131,11 +163,61 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N64, const Z *Y, int64_t ldy,
     check_launch("k_filter");
     if (after_mfma) CHASE_HIP(hipEventRecord(after_mfma, s));
     if (p.splits > 1) {
-        const int64_t total = (int64_t)N * n;
-        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_filter_reduce, dim3(blocks), dim3(256), 0, s, part,
+        hipLaunchKernelGGL(k_filter_reduce, dim3(reduce_blocks(N, n)), dim3(256), 0, s, part,
                            p.splits, N, n, Y, ldy, X, ldx, W, ldw, a, b, g);
         check_launch("k_filter_reduce");
+    }
+}
+
+void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s) {
+    std::vector<FilterPlan> plan;
+    std::vector<FilterCall> live;
+    for (int i = 0; i < count; ++i) {
+        if (calls[i].n <= 0 || calls[i].N <= 0) continue;
+        const FilterPlan p = filter_plan(calls[i].N, calls[i].n);
+        if (p.splits > 1 && !calls[i].part) throw Error(7, "filter_gemm_group: missing partials");
+        plan.push_back(p);
+        live.push_back(calls[i]);
+    }
+    // MFMA launches, one per tile width present (chunks of kMaxGroup).
+    for (int wn = 1; wn <= 10; ++wn) {
+        std::vector<FilterPlan> pw;
+        std::vector<FilterCall> cw;
+        for (size_t i = 0; i < live.size(); ++i)
+            if (plan[i].wn == wn) {
+                pw.push_back(plan[i]);
+                cw.push_back(live[i]);
+            }
+        for (size_t c0 = 0; c0 < pw.size(); c0 += kMaxGroup) {
+            const int m = (int)std::min<size_t>(kMaxGroup, pw.size() - c0);
+            switch (wn) {
+#define CASE(w) \
+    case w: launch_group_wn<w>(pw.data() + c0, cw.data() + c0, m, s); break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+                default: launch_filter_group_wide(wn, pw.data() + c0, cw.data() + c0, m, s);
+            }
+            check_launch("k_filter_group");
+        }
+    }
+    // The split GEMMs' ordered reductions, in one grid per kMaxGroup.
+    std::vector<size_t> split;
+    for (size_t i = 0; i < live.size(); ++i)
+        if (plan[i].splits > 1) split.push_back(i);
+    for (size_t c0 = 0; c0 < split.size(); c0 += kMaxGroup) {
+        const int m = (int)std::min<size_t>(kMaxGroup, split.size() - c0);
+        ReduceGroupArgs G{};
+        G.count = m;
+        int off = 0;
+        for (int j = 0; j < m; ++j) {
+            const size_t i = split[c0 + j];
+            G.start[j] = off;
+            G.p[j] = filter_args(plan[i], live[i]);
+            off += reduce_blocks(live[i].N, live[i].n);
+        }
+        G.start[m] = off;
+        hipLaunchKernelGGL(k_filter_reduce_group, dim3(off), dim3(256), 0, s, G);
+        check_launch("k_filter_reduce_group");
     }
 }
 

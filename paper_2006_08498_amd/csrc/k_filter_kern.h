@@ -14,21 +14,59 @@ namespace filter_detail {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// W = a * (H Y) + b * Y + g * X for one entry, with every rounding spelled
+// out (explicit fused multiply-adds), so the direct, split and grouped
+// launches give bitwise the same value whatever the compiler contracts.
+__device__ __forceinline__ Z filter_epilogue(double sr, double si, Z yv, Z xv, double a,
+                                             double b, double g) {
+    Z o;
+    o.x = __builtin_fma(a, sr, b * yv.x);
+    o.y = __builtin_fma(a, si, b * yv.y);
+    o.x = __builtin_fma(g, xv.x, o.x);
+    o.y = __builtin_fma(g, xv.y, o.y);
+    return o;
+}
+
 __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Arguments of one filter GEMM as the kernels see them.
+struct FilterArgs {
+    const Z *H;
+    int64_t ldh;
+    const Z *Y;
+    int64_t ldy;
+    const Z *X;
+    int64_t ldx;
+    Z *W;
+    int64_t ldw;
+    Z *part;
+    double a, b, g;
+    int N, n, rb_count, cb_count, splits, kchunk;
+};
+
+// Up to this many GEMMs share one grouped launch (the arguments travel as
+// kernel arguments, about 2 KB).
+constexpr int kMaxGroup = 16;
+struct FilterGroupArgs {
+    int count;
+    int start[kMaxGroup + 1];   // first workgroup of each GEMM (multiples of 8)
+    FilterArgs p[kMaxGroup];
+};
+
+// Workgroup `id` of one GEMM's grid: a 64-row block of H times a block of
+// 16*WN columns over one K range.
 template <int WN, int PD, bool FUSED>
-__global__ __launch_bounds__(256) void k_filter(
+__device__ __forceinline__ void filter_tile(
     const Z *__restrict__ H, int64_t ldh, int N, const Z *__restrict__ Y,
     int64_t ldy, const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
     double b, double g, int rb_count, int cb_count, int splits, int kchunk,
-    Z *__restrict__ part) {
+    Z *__restrict__ part, int id) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
 
-    const int id = blockIdx.x;
     const int xcd = id & 7;
     const int local = id >> 3;
     const int per = cb_count * splits;
@@ -167,20 +205,43 @@ __global__ __launch_bounds__(256) void k_filter(
             const double sr = cr[c][v], si = ci[c][v];
             if (FUSED) {
                 const Z yv = Y[(int64_t)row * ldy + col];
-                Z o;
-                o.x = a * sr + b * yv.x;
-                o.y = a * si + b * yv.y;
-                if (g != 0.0) {
-                    const Z xv = X[(int64_t)row * ldx + col];
-                    o.x += g * xv.x;
-                    o.y += g * xv.y;
-                }
-                W[(int64_t)row * ldw + col] = o;
+                const Z xv = g != 0.0 ? X[(int64_t)row * ldx + col] : Z{0.0, 0.0};
+                W[(int64_t)row * ldw + col] = filter_epilogue(sr, si, yv, xv, a, b, g);
             } else {
                 part[((int64_t)sp * N + row) * n + col] = Z{sr, si};
             }
         }
     }
+}
+
+template <int WN, int PD, bool FUSED>
+__global__ __launch_bounds__(256) void k_filter(
+    const Z *__restrict__ H, int64_t ldh, int N, const Z *__restrict__ Y,
+    int64_t ldy, const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
+    double b, double g, int rb_count, int cb_count, int splits, int kchunk,
+    Z *__restrict__ part) {
+    filter_tile<WN, PD, FUSED>(H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, rb_count,
+                               cb_count, splits, kchunk, part, blockIdx.x);
+}
+
+// Several GEMMs of the same tile width in one grid.  Each GEMM's
+// workgroups are a contiguous range starting at a multiple of 8, so a
+// workgroup lands on the same XCD as in a launch of its own.
+template <int WN, int PD>
+__global__ __launch_bounds__(256) void k_filter_group(const FilterGroupArgs G) {
+    const int id = blockIdx.x;
+    int i = 0;
+    while (i + 1 < G.count && id >= G.start[i + 1]) ++i;
+    const FilterArgs &A = G.p[i];
+    const int lid = id - G.start[i];
+    if (A.splits == 1)
+        filter_tile<WN, PD, true>(A.H, A.ldh, A.N, A.Y, A.ldy, A.X, A.ldx, A.W, A.ldw, A.n,
+                                  A.a, A.b, A.g, A.rb_count, A.cb_count, 1, A.kchunk,
+                                  nullptr, lid);
+    else
+        filter_tile<WN, PD, false>(A.H, A.ldh, A.N, A.Y, A.ldy, A.X, A.ldx, A.W, A.ldw, A.n,
+                                   A.a, A.b, A.g, A.rb_count, A.cb_count, A.splits,
+                                   A.kchunk, A.part, lid);
 }
 
 // Prefetch depth per tile width (0 = one step ahead, no ring): narrow
@@ -192,12 +253,54 @@ constexpr int prefetch_depth(int wn) {
 }
 
 
+inline int filter_blocks(const FilterPlan &p) {
+    return (p.rb + 7) / 8 * 8 * p.cb * p.splits;
+}
+
+inline FilterArgs filter_args(const FilterPlan &p, const FilterCall &c) {
+    FilterArgs A;
+    A.H = c.H;
+    A.ldh = c.ldh;
+    A.Y = c.Y;
+    A.ldy = c.ldy;
+    A.X = c.X;
+    A.ldx = c.ldx;
+    A.W = c.W;
+    A.ldw = c.ldw;
+    A.part = p.splits > 1 ? c.part : nullptr;
+    A.a = c.a;
+    A.b = c.b;
+    A.g = c.g;
+    A.N = (int)c.N;
+    A.n = c.n;
+    A.rb_count = p.rb;
+    A.cb_count = p.cb;
+    A.splits = p.splits;
+    A.kchunk = p.kchunk;
+    return A;
+}
+
+// One grouped launch of tile width WN (all plans[i].wn == WN).
+template <int WN>
+void launch_group_wn(const FilterPlan *plans, const FilterCall *calls, int count,
+                     hipStream_t s) {
+    FilterGroupArgs G{};
+    G.count = count;
+    int off = 0;
+    for (int i = 0; i < count; ++i) {
+        G.start[i] = off;
+        G.p[i] = filter_args(plans[i], calls[i]);
+        off += filter_blocks(plans[i]);
+    }
+    G.start[count] = off;
+    hipLaunchKernelGGL((k_filter_group<WN, prefetch_depth(WN)>), dim3(off), dim3(256), 0, s, G);
+}
+
 template <int WN>
 void launch_wn(const FilterPlan &p, const Z *H, int64_t ldh, int N, const Z *Y,
                int64_t ldy, const Z *X, int64_t ldx, Z *W, int64_t ldw, int n,
                double a, double b, double g, Z *part, hipStream_t s) {
-    const int groups = (p.rb + 7) / 8;
-    const int nblocks = groups * 8 * p.cb * p.splits;
+    const int nblocks = filter_blocks(p);
     if (p.splits == 1) {
         hipLaunchKernelGGL((k_filter<WN, prefetch_depth(WN), true>), dim3(nblocks), dim3(256), 0, s,
                            H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, p.rb,

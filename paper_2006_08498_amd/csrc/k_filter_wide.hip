@@ -14,4 +14,12 @@ void launch_filter_wide(const FilterPlan &p, const Z *H, int64_t ldh, int N,
     else throw Error(7, "launch_filter_wide: bad tile width");
 }
 
+void launch_filter_group_wide(int wn, const FilterPlan *plans, const FilterCall *calls,
+                              int count, hipStream_t s) {
+    using namespace filter_detail;
+    if (wn == 9) launch_group_wn<9>(plans, calls, count, s);
+    else if (wn == 10) launch_group_wn<10>(plans, calls, count, s);
+    else throw Error(7, "launch_filter_group_wide: bad tile width");
+}
+
 }  // namespace chase

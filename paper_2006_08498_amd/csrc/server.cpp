@@ -55,6 +55,165 @@ struct Request {
     int slot = -1;
 };
 
+// Cross-request filter fusion.  Each running solve hands the FP64 filter
+// steps of an iteration to the broker (FilterSink::run) instead of
+// launching them.  The broker thread issues ticks on its own stream: a tick
+// is one grouped launch (filter_gemm_group) holding the next step of every
+// solve whose steps are queued, so the tiles of several small problems
+// share one grid.  A solve joins at the next tick once the work before its
+// filter (on its own stream) has finished, and its stream waits for the
+// tick that holds its last step.  At most two ticks are in flight, so a
+// solve that becomes ready waits at most two ticks to join.
+class Broker final : public FilterSink {
+  public:
+    explicit Broker(int device) : device_(device) {
+        CHASE_HIP(hipStreamCreateWithFlags(&fs_, hipStreamNonBlocking));
+        for (auto &e : tick_) CHASE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        th_ = std::thread([this] { loop(); });
+    }
+    ~Broker() override {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        th_.join();
+        (void)hipStreamSynchronize(fs_);
+        for (auto e : tick_) (void)hipEventDestroy(e);
+        for (auto &kv : ev_) {
+            (void)hipEventDestroy(kv.second.first);
+            (void)hipEventDestroy(kv.second.second);
+        }
+        (void)hipStreamDestroy(fs_);
+    }
+
+    // Called by the solve running on stream s (one call at a time per
+    // stream); returns once the steps are enqueued and s waits for them.
+    void run(std::vector<FilterCall> &&steps, hipStream_t s) override {
+        if (steps.empty()) return;
+        Job j;
+        j.steps = std::move(steps);
+        {
+            // Each stream keeps one (ready, done) event pair for its whole
+            // life: re-recording is safe where destroying an event that a
+            // queued wait still refers to would not be.
+            std::lock_guard<std::mutex> lk(m_);
+            auto it = ev_.find(s);
+            if (it == ev_.end()) {
+                hipEvent_t a = nullptr, b = nullptr;
+                CHASE_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+                CHASE_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+                it = ev_.emplace(s, std::make_pair(a, b)).first;
+            }
+            j.ready = it->second.first;
+            j.done = it->second.second;
+        }
+        CHASE_HIP(hipEventRecord(j.ready, s));
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            incoming_.push_back(&j);
+        }
+        cv_.notify_all();
+        {
+            std::unique_lock<std::mutex> lk(m_);
+            cv_job_.wait(lk, [&] { return j.enqueued || j.failed; });
+        }
+        if (j.failed) throw Error(CHASE_EHIP, "fused filter: " + j.error);
+        CHASE_HIP(hipStreamWaitEvent(s, j.done, 0));
+    }
+
+    void stats(int64_t *ticks, int64_t *steps) {
+        std::lock_guard<std::mutex> lk(m_);
+        *ticks = ticks_;
+        *steps = steps_;
+    }
+
+  private:
+    struct Job {
+        std::vector<FilterCall> steps;
+        size_t next = 0;
+        hipEvent_t ready = nullptr, done = nullptr;
+        bool enqueued = false, failed = false;
+        std::string error;
+    };
+
+    void loop() {
+        (void)hipSetDevice(device_);
+        std::vector<Job *> active;
+        std::vector<FilterCall> calls;
+        int64_t issued = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                if (active.empty())
+                    cv_.wait_for(lk, std::chrono::microseconds(200),
+                                 [&] { return stop_ || !incoming_.empty(); });
+                if (stop_ && incoming_.empty() && active.empty()) return;
+                // Jobs whose preceding work is complete join this tick.
+                bool woke = false;
+                for (auto it = incoming_.begin(); it != incoming_.end();) {
+                    const hipError_t q = hipEventQuery((*it)->ready);
+                    if (q == hipSuccess) {
+                        active.push_back(*it);
+                        it = incoming_.erase(it);
+                    } else if (q != hipErrorNotReady) {
+                        (*it)->failed = true;
+                        (*it)->error = hipGetErrorString(q);
+                        it = incoming_.erase(it);
+                        woke = true;
+                    } else {
+                        ++it;
+                    }
+                }
+                if (woke) cv_job_.notify_all();
+            }
+            if (active.empty()) {
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                continue;
+            }
+            try {
+                if (issued >= 2) CHASE_HIP(hipEventSynchronize(tick_[issued % 2]));
+                calls.clear();
+                for (Job *j : active) calls.push_back(j->steps[j->next++]);
+                filter_gemm_group(calls.data(), (int)calls.size(), fs_);
+                CHASE_HIP(hipEventRecord(tick_[issued % 2], fs_));
+                ++issued;
+                std::vector<Job *> still, fin;
+                for (Job *j : active) (j->next == j->steps.size() ? fin : still).push_back(j);
+                for (Job *j : fin) CHASE_HIP(hipEventRecord(j->done, fs_));
+                {
+                    // Once marked, a job belongs to its caller again.
+                    std::lock_guard<std::mutex> lk(m_);
+                    for (Job *j : fin) j->enqueued = true;
+                    ++ticks_;
+                    steps_ += (int64_t)calls.size();
+                }
+                if (!fin.empty()) cv_job_.notify_all();
+                active.swap(still);
+            } catch (const std::exception &e) {
+                std::lock_guard<std::mutex> lk(m_);
+                for (Job *j : active) {
+                    j->failed = true;
+                    j->error = e.what();
+                }
+                active.clear();
+                cv_job_.notify_all();
+            }
+        }
+    }
+
+    int device_;
+    hipStream_t fs_ = nullptr;
+    hipEvent_t tick_[2] = {nullptr, nullptr};
+    std::thread th_;
+    std::mutex m_;
+    std::condition_variable cv_, cv_job_;
+    std::deque<Job *> incoming_;
+    std::map<hipStream_t, std::pair<hipEvent_t, hipEvent_t>> ev_;
+    bool stop_ = false;
+    int64_t ticks_ = 0, steps_ = 0;
+};
+
 }  // namespace
 
 struct chase_server {
@@ -71,6 +230,7 @@ struct chase_server {
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     int device = 0;
+    std::unique_ptr<Broker> broker;   // CHASE_SERVER_FUSE_FILTER
 };
 
 namespace {
@@ -117,7 +277,7 @@ void run_one(chase_server *s, Request *r, int slot) {
             }
             H = reinterpret_cast<const Z *>(dH);
         }
-        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts};
+        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts, s->broker.get()};
         Result R = solve(p, dW, reinterpret_cast<Z *>(dV), r->N, st);
         r->eigvals = std::move(R.eigvals);
         r->resid = std::move(R.resid);
@@ -207,9 +367,16 @@ int submit_common(chase_server *s, std::unique_ptr<Request> r, uint64_t *ticket)
 
 extern "C" {
 
-chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots) {
+chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots, uint32_t flags) {
     try {
-        if (max_slots < 1 || max_slots > 64) return nullptr;
+        if (max_slots < 1 || max_slots > 64) {
+            g_srv_err = "max_slots must be in [1, 64]";
+            return nullptr;
+        }
+        if (flags & ~(uint32_t)CHASE_SERVER_FUSE_FILTER) {
+            g_srv_err = "unknown server flags";
+            return nullptr;
+        }
         auto *s = new chase_server();
         CHASE_HIP(hipGetDevice(&s->device));
         if (hbm_budget_bytes == 0) {
@@ -225,6 +392,7 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots) {
             CHASE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             s->streams.push_back(st);
         }
+        if (flags & CHASE_SERVER_FUSE_FILTER) s->broker = std::make_unique<Broker>(s->device);
         for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker, s, i);
         return s;
     } catch (const std::exception &e) {
@@ -330,6 +498,13 @@ int chase_server_wait(chase_server *s, uint64_t ticket, double timeout_s) {
     return done() ? CHASE_OK : CHASE_PENDING;
 }
 
+int chase_server_fusion_stats(chase_server *s, int64_t *ticks, int64_t *steps) {
+    if (!s || !ticks || !steps) return srv_fail(CHASE_EINVAL, "NULL argument");
+    *ticks = *steps = 0;
+    if (s->broker) s->broker->stats(ticks, steps);
+    return CHASE_OK;
+}
+
 int chase_server_stats(chase_server *s, size_t *bytes_in_use, size_t *peak_bytes,
                        int32_t *running, int32_t *peak_running, int32_t *queued) {
     if (!s) return srv_fail(CHASE_EINVAL, "NULL server");
@@ -353,6 +528,7 @@ void chase_server_destroy(chase_server *s) {
     }
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
+    s->broker.reset();
     for (auto &kv : s->reqs)
         if (kv.second->dV) (void)hipFree(kv.second->dV);
     for (auto st : s->streams) (void)hipStreamDestroy(st);

@@ -89,34 +89,21 @@ Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o) {
 // steps, so step s runs on the suffix of columns with deg >= s.  Two
 // buffers: V holds Y_0 and every even iterate, B1 every odd iterate, each
 // step writing over the older iterate in place.
-void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
-                  int n, const int *deg, double mu1, double alpha, double beta,
-                  Z *fpart, hipStream_t s, std::vector<hipEvent_t> *prof) {
-    if (n <= 0) return;
+std::vector<FilterCall> filter_steps(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1,
+                                     int64_t ld, int n, const int *deg, double mu1,
+                                     double alpha, double beta, Z *fpart) {
+    std::vector<FilterCall> out;
+    if (n <= 0) return out;
     const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
     const double sigma1 = e / (mu1 - c);
     const double tau = 2.0 / sigma1;
     const int mmax = deg[n - 1];
-    auto launch = [&](const Z *Y, const Z *X, Z *W, int cols, double a, double b,
-                      double g) {
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-        if (prof) {
-            CHASE_HIP(hipEventCreate(&e0));
-            CHASE_HIP(hipEventCreate(&e1));
-            CHASE_HIP(hipEventCreate(&e2));
-            CHASE_HIP(hipEventRecord(e0, s));
-        }
-        filter_gemm(H, ldh, N, Y, ld, X, ld, W, ld, cols, a, b, g, fpart, s, e1);
-        if (prof) {
-            CHASE_HIP(hipEventRecord(e2, s));
-            prof->push_back(e0);
-            prof->push_back(e1);
-            prof->push_back(e2);
-        }
+    auto step = [&](const Z *Y, const Z *X, Z *W, int cols, double a, double b, double g) {
+        out.push_back(FilterCall{H, ldh, N, Y, ld, X, ld, W, ld, cols, a, b, g, fpart});
     };
     {
         const double a = sigma1 / e;
-        launch(V, nullptr, B1, n, a, -c * a, 0.0);
+        step(V, nullptr, B1, n, a, -c * a, 0.0);
     }
     double sprev = sigma1;
     int first = 0;
@@ -126,9 +113,33 @@ void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
         const double g = -sprev * sigma;
         while (first < n && deg[first] < st) ++first;
         const int cols = n - first;
-        if (st % 2 == 0) launch(B1 + first, V + first, V + first, cols, a, -c * a, g);
-        else launch(V + first, B1 + first, B1 + first, cols, a, -c * a, g);
+        if (st % 2 == 0) step(B1 + first, V + first, V + first, cols, a, -c * a, g);
+        else step(V + first, B1 + first, B1 + first, cols, a, -c * a, g);
         sprev = sigma;
+    }
+    return out;
+}
+
+void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
+                  int n, const int *deg, double mu1, double alpha, double beta,
+                  Z *fpart, hipStream_t s, std::vector<hipEvent_t> *prof) {
+    for (const FilterCall &f :
+         filter_steps(H, ldh, N, V, B1, ld, n, deg, mu1, alpha, beta, fpart)) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (prof) {
+            CHASE_HIP(hipEventCreate(&e0));
+            CHASE_HIP(hipEventCreate(&e1));
+            CHASE_HIP(hipEventCreate(&e2));
+            CHASE_HIP(hipEventRecord(e0, s));
+        }
+        filter_gemm(f.H, f.ldh, f.N, f.Y, f.ldy, f.X, f.ldx, f.W, f.ldw, f.n, f.a, f.b, f.g,
+                    f.part, s, e1);
+        if (prof) {
+            CHASE_HIP(hipEventRecord(e2, s));
+            prof->push_back(e0);
+            prof->push_back(e1);
+            prof->push_back(e2);
+        }
     }
 }
 
@@ -456,8 +467,14 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
                 c2z_block(Vc, n32, V + L, ne, N, n32, s);
                 for (int j = L; j < L + n32; ++j) info.matvecs_filter_fp32 += deg[j];
             }
-            filter_block(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne, n - n32,
-                         deg.data() + L + n32, mu1, alpha, beta, fpart, s, profp);
+            if (p.sink)
+                p.sink->run(filter_steps(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne,
+                                         n - n32, deg.data() + L + n32, mu1, alpha, beta,
+                                         fpart),
+                            s);
+            else
+                filter_block(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne, n - n32,
+                             deg.data() + L + n32, mu1, alpha, beta, fpart, s, profp);
             for (int j = L; j < ne; ++j) info.matvecs_filter += deg[j];
         }
         CHASE_HIP(hipEventRecord(ev[1], s));

@@ -23,6 +23,15 @@ struct Layout {
 int internal_nex(int64_t N, int nev, int nex);
 Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o);
 
+// Where a solve sends the FP64 filter steps of one iteration instead of
+// launching them itself (the server's cross-request fusion).  run() must
+// leave the steps ordered after the work already on `s`, and the work
+// enqueued on `s` afterwards ordered after them.
+struct FilterSink {
+    virtual void run(std::vector<FilterCall> &&steps, hipStream_t s) = 0;
+    virtual ~FilterSink() = default;
+};
+
 struct Problem {
     const Z *H;
     int64_t N, ldh;
@@ -30,6 +39,7 @@ struct Problem {
     double tol;
     int degree_max;
     chase_opts opts;
+    FilterSink *sink = nullptr;
 };
 
 struct Result {
@@ -41,6 +51,11 @@ struct Result {
 // Runs the solve; eigenvectors (column-major, ldv) go to dV.
 Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv,
              hipStream_t s);
+
+// The filter's GEMMs for one iteration, in order (see filter_block).
+std::vector<FilterCall> filter_steps(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1,
+                                     int64_t ld, int n, const int *deg, double mu1,
+                                     double alpha, double beta, Z *fpart);
 
 // Step-level helpers shared with the C ABI.
 void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,

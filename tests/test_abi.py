@@ -123,3 +123,17 @@ def test_lanczos_bounds_match_oracle():
     got = chase.lanczos_bounds(al, be, N, ne)
     ref = steps.lanczos_bounds(al, be, N, ne)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_group_and_server_arguments_rejected_without_device_work():
+    L = chase.lib()
+    assert L.chase_filter_step_group(None, -1, None) == chase.CHASE_EINVAL
+    assert L.chase_filter_step_group(None, 2, None) == chase.CHASE_EINVAL
+    bad = (chase.FilterCall * 1)()
+    bad[0] = chase.FilterCall(16, 10, 5, 16, 4, None, 4, 32, 4, 4, 1.0, 0.0, 0.0)  # ldh < N
+    assert L.chase_filter_step_group(ctypes.cast(bad, ctypes.c_void_p), 1, None) == \
+        chase.CHASE_EINVAL
+    assert "leading dimension" in chase.last_error()
+    assert L.chase_server_create(0, 2, 8) is None
+    assert b"flags" in L.chase_server_last_error()
+    assert L.chase_server_create(0, 0, 0) is None

@@ -40,6 +40,27 @@ def test_results_same_alone_and_in_the_mix():
         assert b.latency_s >= b.gpu_s >= 0 and b.queued_s >= 0
 
 
+def test_fused_filter_same_results_and_fuses():
+    """With cross-request filter fusion the results are bitwise the solo
+    ones, and the grouped launches really held steps of several solves."""
+    torch_cuda()
+    mats = [dev_colmajor(synth.dk_matrix(N, seed=s)) for N, _, _, s in CASES]
+    solo = [_solo(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, CASES)]
+    with chase.Server(slots=4, fuse=True) as srv:
+        tickets = [srv.submit(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, CASES)]
+        outs = []
+        for t in tickets:
+            assert srv.wait(t, timeout=120.0)
+            outs.append(srv.poll(t))
+        st = srv.stats()
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a.eigvals, b.eigvals)
+        assert np.array_equal(host(a.V), host(b.V))
+    total = sum(r.info["matvecs_filter"] for r in outs)
+    assert st["fused_ticks"] > 0 and st["fused_steps"] > st["fused_ticks"]
+    assert st["fused_steps"] <= total
+
+
 def test_budget_admits_one_at_a_time():
     torch = torch_cuda()
     same = [(2600, 20, 8, 31), (2600, 20, 8, 32), (2600, 20, 8, 33)]

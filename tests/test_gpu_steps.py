@@ -62,6 +62,30 @@ def test_filter_step_zero_g_without_X():
     assert np.all(np.abs(W - ref) <= dot_bound(np.abs(H), np.abs(Y), N))
 
 
+def test_filter_step_group_bitwise_equals_single_steps():
+    """One grouped launch over steps of different N, n (tile widths 1..10,
+    split and unsplit plans, several column blocks), with and without X, one
+    of them in place: each result is bitwise the single step's, which the
+    elementwise test above pins to the oracle."""
+    torch = torch_cuda()
+    shapes = [(1, 1), (63, 16), (700, 33), (1301, 140), (2049, 161), (4100, 16),
+              (5000, 150), (3000, 9), (257, 64)]
+    steps_g, singles = [], []
+    for k, (N, n) in enumerate(shapes):
+        H = dev_colmajor(synth.dk_matrix(N, seed=100 + k))
+        Y = dev_block(synth.random_block(N, n, seed=200 + k))
+        X = dev_block(synth.random_block(N, n, seed=300 + k))
+        a, b, g = 0.37 + 0.01 * k, -1.3, (0.0 if k % 3 == 0 else 0.55)
+        Xs = None if g == 0.0 else X
+        singles.append(host(chase.filter_step(H, Y, Xs, a, b, g)))
+        W = X if k == 4 else torch.empty_like(Y)      # one in-place update
+        steps_g.append((H, Y, Xs, W, a, b, g))
+    chase.filter_step_group(steps_g)
+    for (H, Y, X, W, a, b, g), ref in zip(steps_g, singles):
+        assert np.array_equal(host(W), ref)
+    chase.filter_step_group([])                          # empty group is a no-op
+
+
 def test_filter_per_vector_degrees_vs_oracle_and_closed_form():
     torch_cuda()
     N = 700
