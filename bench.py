@@ -80,6 +80,7 @@ def run_serve(args):
                                  cfg["decay"], 1.0, 6.0, ctypes.c_void_p(stream))
         return fill
 
+    precision = chase.CHASE_MIXED if args.serve_precision == "mixed" else chase.CHASE_FP64
     srv = chase.Server(budget_bytes=0, slots=args.slots, fuse=args.fuse)
     log(f"serving {len(sched)} requests over {sched[-1]['t']:.1f} s with "
         f"{args.slots} slots")
@@ -92,7 +93,8 @@ def run_serve(args):
         while i < len(sched) and sched[i]["t"] <= now:
             q = sched[i]
             tk = srv.submit_fill(make_fill(q["seed"]), q["N"], q["nev"], q["nex"],
-                                 cfg["tol"], cfg["degree_max"], profile=1)
+                                 cfg["tol"], cfg["degree_max"], profile=1,
+                                 precision=precision)
             pending[tk] = q
             i += 1
         for tk in list(pending):
@@ -133,10 +135,11 @@ def run_serve(args):
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == chase.CHASE_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "serve128: 128 requests, Poisson 4/s, N in {4k..20k} D+K, "
                                "nev in [30,150], nex=0.4 nev, tol 1e-10, degree<=20",
+                   "precision": args.serve_precision,
                    "slots": args.slots, "fuse_filter": bool(args.fuse),
                    "parallelism": "1 GPU"},
         "p50_s": p50, "p99_s": p99,
@@ -150,9 +153,10 @@ def run_serve(args):
         "check": {"max_resid_rel_sampled": worst},
     }
     if args.serve_solo_baseline:
-        # The same requests solved one after another, each alone on the GPU.
+        # The same requests solved one after another, each alone on the GPU
+        # with the plain FP64 path.
         t_solo = 0.0
-        for q, _, _ in done:
+        for i, (q, _, _) in enumerate(done):
             H = synth.dk_matrix_device(q["N"], seed=q["seed"], std=cfg["std"],
                                        decay=cfg["decay"])
             torch.cuda.synchronize()
@@ -160,8 +164,10 @@ def run_serve(args):
             chase.solve(H, q["nev"], q["nex"], cfg["tol"], cfg["degree_max"])
             t_solo += time.perf_counter() - a
             del H
-        out["solo_sum_s"] = t_solo
-        out["speedup_served_over_solo"] = t_solo / makespan
+            if (i + 1) % 16 == 0:
+                log(f"solo baseline: {i + 1} solves, {t_solo:.1f} s")
+        out["solo_fp64_sum_s"] = t_solo
+        out["speedup_served_over_solo_fp64"] = t_solo / makespan
     print(json.dumps(out), flush=True)
 
 
@@ -275,6 +281,8 @@ def main():
     ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
     ap.add_argument("--fuse", type=int, default=0,
                     help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
+    ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64",
+                    help="serve128: precision of the served solves")
     ap.add_argument("--serve-solo-baseline", action="store_true",
                     help="serve128: also time every request alone, one after another")
     ap.add_argument("--seed", type=int, default=0)

@@ -131,6 +131,9 @@ typedef struct chase_info {
      * (8 N^2 per column) and launch count */
     double gemm_time, gemm_flops;
     int64_t gemm_launches;
+    /* iterations spent on a whole-block Rayleigh-Ritz (no filter) after the
+     * first active pair stalled just above tol behind the locked ones */
+    int64_t refinements;
 } chase_info;
 
 /* Fills *o with the defaults listed above. */

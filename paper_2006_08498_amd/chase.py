@@ -88,6 +88,7 @@ class ChaseInfo(ctypes.Structure):
         ("gemm_time", ctypes.c_double),
         ("gemm_flops", ctypes.c_double),
         ("gemm_launches", ctypes.c_int64),
+        ("refinements", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -447,6 +447,11 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     std::vector<double> res_prev(ne, INFINITY), pred_gain(ne, 1.0);
     std::vector<int> rdeg(ne, d0);           // degrees in Ritz order
     int n32 = Lo.mixed ? ne : 0;             // FP32 columns leading the filter order
+    // Residual of each Ritz position at the previous iteration, and the
+    // whole-block refinement state (see the stagnation test below).
+    std::vector<double> res_last(ne, INFINITY);
+    bool refine = false;
+    int last_refine = -100;
     int L = 0;
     int it = 0;
     int qr_salt = 0;
@@ -458,7 +463,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         const double e_half = 0.5 * (beta - alpha);
         // When the search space is the whole space (ne == N) Rayleigh-Ritz
         // is exact and filtering would only make the block ill-conditioned.
-        if (ne < N && e_half > 1e-14 * std::max(1.0, std::fabs(beta))) {
+        if (!refine && ne < N && e_half > 1e-14 * std::max(1.0, std::fabs(beta))) {
             // Active columns: the FP32 group first, each group by degree.
             if (n32 > 0) {
                 z2c_block(V + L, ne, Vc, n32, N, n32, s);
@@ -518,6 +523,31 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         info.mu1 = mu1;
         const bool stop = o.on_iteration && o.on_iteration(o.on_iteration_user, &info) != 0;
         if (L >= nev || it == o.max_iter || stop) break;
+        // Stagnation just above tol.  A pair locked with a residual just
+        // under tol_abs keeps components of its neighbours' eigenvectors
+        // (about residual / gap), and every active vector is kept orthogonal
+        // to it, so the next vector's residual can stall near tol_abs while
+        // the block's span is already accurate.  One Rayleigh-Ritz over the
+        // whole block (locked columns included, no filter) splits that span
+        // afresh; locking then restarts from the prefix.
+        const bool refined_now = refine;
+        refine = false;
+        if (!refined_now && L > 0 && L < ne && it - last_refine >= 3 &&
+            res[L] <= 8.0 * tol_abs && std::isfinite(res_last[L]) &&
+            res_last[L] / res[L] < 1.5 && !(Lo.mixed && fp32[L])) {
+            refine = true;
+            last_refine = it;
+            ++info.refinements;
+        }
+        for (int j = L; j < ne; ++j) res_last[j] = res[j];
+        if (refine) {
+            for (int j = 0; j < L; ++j) {
+                fp32[j] = 0;
+                use64[j] = 1;
+                res_prev[j] = res[j];
+            }
+            L = 0;
+        }
         // Filter interval, rates and degrees for the next iteration.  The
         // per-vector state is kept in Ritz order (position j = j-th smallest
         // Ritz value of the active block, as Rayleigh-Ritz returns it); only

@@ -189,3 +189,20 @@ def test_iteration_callback_reports_and_stops():
     assert stop.info["iterations"] == 2
     assert stop.status == (chase.CHASE_OK if seen[1]["nconv"] >= 12 else chase.CHASE_ENOCONV)
     assert stop.info["nconv"] == seen[1]["nconv"]
+
+
+def test_stall_behind_locked_pairs_is_refined():
+    """A served request (N = 16000 D + K, seed 1086) whose pair 117 stalled
+    at 1.4e-10 * ||H|| behind pairs locked just under tol: the whole-block
+    Rayleigh-Ritz step must let it converge, in both precisions."""
+    torch_cuda()
+    N, nev, nex = 16000, 119, 48
+    H = synth.dk_matrix_device(N, seed=1086, std=0.02, decay=200.0)
+    out = {}
+    for prec in (chase.CHASE_MIXED, chase.CHASE_FP64):
+        r = chase.solve(H, nev, nex, 1e-10, 20, precision=prec)
+        assert r.status == chase.CHASE_OK and r.info["iterations"] < 60
+        assert np.all(r.resid <= 1e-10 * r.info["hnorm_est"])
+        out[prec] = r
+    a, b = out[chase.CHASE_MIXED], out[chase.CHASE_FP64]
+    assert np.abs(a.eigvals - b.eigvals).max() <= 1e-10 * np.abs(b.eigvals).max()
