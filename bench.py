@@ -238,7 +238,7 @@ def cpu_baseline(w, seed, budget_s):
                       f"family took {t:.2f} s; scaled by (N/{ns2})^3 to N={N}"}
 
 
-def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None):
+def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs=None):
     """warmup untimed solves, then `steps` timed solves (the library call is
     synchronous); returns the info records, seconds per solve, last result."""
     import torch
@@ -247,6 +247,8 @@ def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None):
     opts = dict(profile=1, seed=seed, precision=precision)
     if switch_tol is not None:
         opts["switch_tol"] = switch_tol
+    if graphs is not None:
+        opts["graphs"] = graphs
     if N >= 50000:
         # Long solves report each iteration as it ends.
         def progress(info):
@@ -294,6 +296,9 @@ def main():
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="mixed workloads: residual / ||H|| above which a vector is "
                          "filtered in FP32 (library default if omitted)")
+    ap.add_argument("--graphs", type=int, choices=(0, 1), default=None,
+                    help="Jacobi sweeps as HIP graph replays (1) or direct launches (0); "
+                         "library default if omitted")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="mixed workloads: skip timing the plain FP64 solve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -349,7 +354,7 @@ def main():
     o = chase.default_opts(precision=precision)
     ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8, device="cuda")
     infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed,
-                               args.switch_tol)
+                               args.switch_tol, args.graphs)
     chk = check_result(H, r, lam, w["tol"])
     log(f"check: {chk}")
 
@@ -387,6 +392,28 @@ def main():
             # H once plus Y, X and W blocks: 16 N^2 + 48 N per column
             "algorithmic_bytes_per_launch":
                 16.0 * N * N + 48.0 * N * (flops_k / unit) / max(n_k, 1)}
+    # Fraction of roofline per phase: the shortest time the phase's
+    # algorithmic flops and bytes allow at the published peaks (FP64 MFMA,
+    # or FP32 MFMA for the FP32 filter work; 8 TB/s HBM) over the time taken.
+    def mean(k):
+        return float(np.mean([i[k] for i in infos]))
+    f32 = unit * mean("matvecs_filter_fp32")
+    f64 = mean("filter_flops") - f32
+    ph = {"lanczos": (mean("lanczos_flops"), 0.0, mean("lanczos_bytes"), mean("t_lanczos")),
+          "filter": (f64, f32, mean("filter_bytes"), mean("t_filter")),
+          "qr": (mean("qr_flops"), 0.0, mean("qr_bytes"), mean("t_qr")),
+          "rr": (mean("rr_flops"), 0.0, mean("rr_bytes"), mean("t_rr")),
+          "resid": (mean("resid_flops"), 0.0, mean("resid_bytes"), mean("t_resid"))}
+    phase_roof = {}
+    for name, (fl64, fl32, by, t) in ph.items():
+        t_mfma = fl64 / (FP64_PEAK_TFLOPS * 1e12) + fl32 / (FP32_PEAK_TFLOPS * 1e12)
+        t_hbm = by / (HBM_PEAK_GBS * 1e9)
+        phase_roof[name] = {
+            "s": t, "tflops": (fl64 + fl32) / t / 1e12 if t > 0 else 0.0,
+            "gbs": by / t / 1e9 if t > 0 else 0.0,
+            "bound": "mfma" if t_mfma >= t_hbm else "hbm",
+            "frac": max(t_mfma, t_hbm) / t if t > 0 else 0.0}
+
     from paper_2006_08498_amd import profsum
     rec = profsum.read_record(os.path.join(ROOT, "profiles", f"{kern}_{args.workload}.md"))
     if rec and rec.get("sources_digest") == profsum.sources_digest(kern) \
@@ -423,6 +450,7 @@ def main():
         "matvecs_filter": infos[-1]["matvecs_filter"],
         "matvecs_filter_fp32": infos[-1]["matvecs_filter_fp32"],
         "phases_s": phases,
+        "phase_roofline": phase_roof,
         "check": chk,
         "roofline": roof,
     }

@@ -92,7 +92,11 @@ typedef struct chase_opts {
                                  random start */
     int32_t profile;          /* 1: time every filter launch with HIP events
                                  (fills t_filter_kernels) */
-    int32_t reserved0;
+    int32_t graphs;           /* 1: run each Jacobi sweep of the Rayleigh-Ritz
+                                 eigensolve as one replay of a captured HIP
+                                 graph (captured once per order); 0: launch
+                                 the sweep's kernels one by one.  Same
+                                 results either way. */
     /* Optional, called on the host thread running the solve (a server's
      * worker thread for served requests) after every subspace iteration with the record so far (iterations, nconv = locked pairs,
      * counters and phase times; alpha/mu1 of that iteration).  A nonzero
@@ -134,6 +138,18 @@ typedef struct chase_info {
     /* iterations spent on a whole-block Rayleigh-Ritz (no filter) after the
      * first active pair stalled just above tol behind the locked ones */
     int64_t refinements;
+    /* Algorithmic work of each phase over the whole solve (what the method
+     * must do, not what the kernels happen to move): flops in real
+     * operations (a complex multiply-add is 8) and HBM bytes with every
+     * operand read once and every result written once.  Lanczos: k steps of
+     * H times r vectors plus the vector updates; filter (both precisions):
+     * H (16 or 8 N^2 bytes) once per launch plus the Y, X and W columns;
+     * QR: two Gram-Schmidt passes against the locked columns and three
+     * CholeskyQR passes; Rayleigh-Ritz: W = H Q, Q^H W and Q Y (the small
+     * eigensolve is not counted); residuals: W Y, the norms and the copy
+     * back. */
+    double lanczos_flops, lanczos_bytes, filter_bytes, qr_flops, qr_bytes, rr_flops,
+        rr_bytes, resid_flops, resid_bytes;
 } chase_info;
 
 /* Fills *o with the defaults listed above. */

@@ -54,7 +54,7 @@ class ChaseOpts(ctypes.Structure):
         ("switch_tol", ctypes.c_double),
         ("dV0", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
         ("on_iteration", ctypes.c_void_p),
         ("on_iteration_user", ctypes.c_void_p),
         ("reserved", ctypes.c_int32 * 2),
@@ -89,6 +89,15 @@ class ChaseInfo(ctypes.Structure):
         ("gemm_flops", ctypes.c_double),
         ("gemm_launches", ctypes.c_int64),
         ("refinements", ctypes.c_int64),
+        ("lanczos_flops", ctypes.c_double),
+        ("lanczos_bytes", ctypes.c_double),
+        ("filter_bytes", ctypes.c_double),
+        ("qr_flops", ctypes.c_double),
+        ("qr_bytes", ctypes.c_double),
+        ("rr_flops", ctypes.c_double),
+        ("rr_bytes", ctypes.c_double),
+        ("resid_flops", ctypes.c_double),
+        ("resid_bytes", ctypes.c_double),
     ]
 
     def as_dict(self):

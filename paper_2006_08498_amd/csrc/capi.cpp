@@ -98,6 +98,7 @@ void validate_opts(const chase_opts &o) {
     REQUIRE(o.lanczos_steps >= 1, "lanczos_steps must be >= 1");
     REQUIRE(o.lanczos_runs >= 1 && o.lanczos_runs <= 64, "lanczos_runs must be in [1, 64]");
     REQUIRE(o.switch_tol > 0.0, "switch_tol must be > 0");
+    REQUIRE(o.graphs == 0 || o.graphs == 1, "graphs must be 0 or 1");
 }
 
 }  // namespace
@@ -117,6 +118,7 @@ void chase_default_opts(chase_opts *o) {
     o->switch_tol = 1e-7;
     o->dV0 = nullptr;
     o->profile = 0;
+    o->graphs = 1;
 }
 
 const char *chase_last_error(void) { return g_err.c_str(); }

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 namespace chase {
 
@@ -152,9 +153,27 @@ void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
 // Reduced Hermitian eigenproblem by cyclic Jacobi.  A: n x n row-major
 // (overwritten).  On return w (device, ascending) and Y (row-major, columns
 // are eigenvectors).  work: jacobi_work_elems(n) complex elements.
+// Jacobi sweeps captured as HIP graphs (one per order n and buffer set,
+// one for each ping-pong parity) and replayed once per sweep; owned by one
+// solve, which passes it to every jacobi_eig call.
+struct JacobiGraphs {
+    struct Entry {
+        int n;
+        const void *A, *work;
+        hipGraphExec_t exec[2];
+    };
+    hipStream_t cap = nullptr;   // capture stream (never runs work)
+    hipStream_t used = nullptr;  // stream the graphs were launched on
+    std::vector<Entry> entries;
+    JacobiGraphs() = default;
+    JacobiGraphs(const JacobiGraphs &) = delete;
+    JacobiGraphs &operator=(const JacobiGraphs &) = delete;
+    ~JacobiGraphs();
+};
+size_t jacobi_work_elems(int n);
 size_t jacobi_work_elems(int n);
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
-                hipStream_t s);
+                hipStream_t s, JacobiGraphs *graphs = nullptr);
 // Symmetrise: G <- (G + G^H)/2, real diagonal.
 void hermitise(Z *G, int n, hipStream_t s);
 

@@ -25,79 +25,111 @@ __device__ __forceinline__ Z zsub(Z a, Z b) { return Z{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------- CholeskyQR
-// One workgroup.  G (n x n row-major) -> lower Cholesky factor of
-// D G D + shift I in place; B = D L^{-H}; Linv in `work`.
+// CholeskyQR factor, one workgroup of 1024 threads: G (n x n row-major,
+// n <= 1024) -> B = D L^{-H} (upper triangular, row-major) with L the lower
+// Cholesky factor of D G D + shift I and D = diag(G)^{-1/2}.  `work` holds
+// D and X = L^{-1}.  *info = 0, or k + 1 for a non-positive pivot k (then
+// B is not written).  Both halves are right-looking, one step per column:
+//  * Cholesky step k: scale column k by 1/sqrt(pivot), then subtract the
+//    rank-1 product of column k from the trailing lower triangle;
+//  * inversion step k: X[k][j] *= 1/L[k][k] for j <= k, then
+//    X[i][j] -= L[i][k] X[k][j] for i > k, j <= k.
+// Each step's serial input (column k of the updated matrix, with its
+// pivot; row k of X) is handed over through LDS by the previous step's
+// update instead of being re-read from memory, so a step waits on L2 once
+// (its own update) rather than three times.
+
 __global__ __launch_bounds__(1024) void k_chol_factor(Z *G, int n, double shift,
                                                       Z *B, Z *work,
                                                       int *info) {
     __shared__ int bad;
+    __shared__ Z colk[1024], nxt[1024], rowk[1024];
+    __shared__ double ldiag[1024];
     const int t = threadIdx.x, nt = blockDim.x;
     double *dsc = reinterpret_cast<double *>(work);          // n doubles
-    Z *Linv = work + (n + 1) / 2 + 1;                        // n x n
-    if (t == 0) bad = 0;
+    Z *X = work + (n + 1) / 2 + 1;                           // n x n
+    if (t == 0) bad = 0x7fffffff;
     __syncthreads();
     for (int j = t; j < n; j += nt) {
         const double gjj = G[(int64_t)j * n + j].x;
-        if (!(gjj > 0.0) || !isfinite(gjj)) bad = j + 1;
+        if (!(gjj > 0.0) || !isfinite(gjj)) atomicMin(&bad, j + 1);   // LDS atomic
         dsc[j] = gjj > 0.0 ? 1.0 / sqrt(gjj) : 0.0;
     }
     __syncthreads();
-    if (bad) {
+    if (bad != 0x7fffffff) {
         if (t == 0) *info = bad;
         return;
     }
-    // Scale and shift (lower triangle only is used below).
-    for (int64_t e = t; e < (int64_t)n * n; e += nt) {
-        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    // Scale and shift (lower triangle only is used below); X = I; column 0
+    // of the scaled matrix into LDS.
+    for (int e = t; e < n * n; e += nt) {
+        const int i = e / n, j = e - i * n;
+        X[e] = Z{i == j ? 1.0 : 0.0, 0.0};
         if (j > i) continue;
         Z v = zscale(G[e], dsc[i] * dsc[j]);
         if (i == j) v = Z{v.x + shift, 0.0};
         G[e] = v;
+        if (j == 0) nxt[i] = v;
     }
     __syncthreads();
-    // Right-looking Cholesky, lower.
+    // Right-looking Cholesky, lower.  nxt holds column k (rows >= k).
     for (int k = 0; k < n; ++k) {
-        const double piv = G[(int64_t)k * n + k].x;
+        const double piv = nxt[k].x;
         if (!(piv > 0.0) || !isfinite(piv)) {
             if (t == 0) *info = k + 1;
             return;   // uniform: every thread read the same pivot
         }
         const double l = sqrt(piv), il = 1.0 / l;
+        for (int i = k + 1 + t; i < n; i += nt) {
+            const Z v = zscale(nxt[i], il);
+            G[(int64_t)i * n + k] = v;
+            colk[i] = v;
+        }
+        if (t == 0) {
+            G[(int64_t)k * n + k] = Z{l, 0.0};
+            ldiag[k] = l;
+        }
         __syncthreads();
-        for (int i = k + 1 + t; i < n; i += nt)
-            G[(int64_t)i * n + k] = zscale(G[(int64_t)i * n + k], il);
-        __syncthreads();
-        if (t == 0) G[(int64_t)k * n + k] = Z{l, 0.0};
         const int m = n - k - 1;
-        const int64_t cnt = (int64_t)m * (m + 1) / 2;
-        for (int64_t e = t; e < cnt; e += nt) {
-            // e -> (ii, jj) with jj <= ii in the trailing block
-            int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-            while ((int64_t)ii * (ii + 1) / 2 > e) --ii;
-            while ((int64_t)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-            const int jj = (int)(e - (int64_t)ii * (ii + 1) / 2);
+        for (int e = t; e < m * m; e += nt) {
+            const int ii = e / m, jj = e - ii * m;
+            if (jj > ii) continue;
             const int i = k + 1 + ii, j = k + 1 + jj;
-            const Z lik = G[(int64_t)i * n + k], ljk = G[(int64_t)j * n + k];
-            G[(int64_t)i * n + j] = zsub(G[(int64_t)i * n + j], zmul(lik, zconj(ljk)));
+            const Z v = zsub(G[(int64_t)i * n + j], zmul(colk[i], zconj(colk[j])));
+            G[(int64_t)i * n + j] = v;
+            if (jj == 0) nxt[i] = v;   // column k + 1 for the next step
         }
         __syncthreads();
     }
-    // Columns of L^{-1} by forward substitution, one thread per column;
-    // thread j also writes row j of B = D L^{-H}.
-    for (int j = t; j < n; j += nt) {
-        const Z ljj = G[(int64_t)j * n + j];
-        Linv[(int64_t)j * n + j] = Z{1.0 / ljj.x, 0.0};
-        for (int i = j + 1; i < n; ++i) {
-            Z s{0.0, 0.0};
-            for (int k = j; k < i; ++k)
-                s = zadd(s, zmul(G[(int64_t)i * n + k], Linv[(int64_t)k * n + j]));
-            Linv[(int64_t)i * n + j] = zscale(s, -1.0 / G[(int64_t)i * n + i].x);
+    // X = L^{-1}, right-looking.  rowk holds row k of X (entries <= k);
+    // thread t prefetches L[k + 2 + t][k + 1] for the next step.
+    if (t == 0) nxt[0] = Z{1.0, 0.0};
+    Z lnext = (1 + t < n) ? G[(int64_t)(1 + t) * n + 0] : Z{0.0, 0.0};
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double xkk = 1.0 / ldiag[k];
+        for (int j = t; j <= k; j += nt) {
+            const Z x = zscale(nxt[j], xkk);
+            X[(int64_t)k * n + j] = x;
+            rowk[j] = x;
         }
-        for (int i = 0; i < n; ++i) {
-            // B[j][i] = d_j * conj(Linv[i][j]) (zero below the diagonal)
-            B[(int64_t)j * n + i] =
-                i >= j ? zscale(zconj(Linv[(int64_t)i * n + j]), dsc[j]) : Z{0.0, 0.0};
+        if (k + 1 + t < n) colk[k + 1 + t] = lnext;
+        if (k + 2 + t < n) lnext = G[(int64_t)(k + 2 + t) * n + (k + 1)];
+        __syncthreads();
+        const int w = k + 1, m = n - k - 1;
+        for (int e = t; e < m * w; e += nt) {
+            const int ii = e / w, j = e - ii * w;
+            const int i = k + 1 + ii;
+            const Z v = zsub(X[(int64_t)i * n + j], zmul(colk[i], rowk[j]));
+            X[(int64_t)i * n + j] = v;
+            if (ii == 0) nxt[j] = v;   // row k + 1 for the next step
         }
+        if (t == 0 && k + 1 < n) nxt[k + 1] = Z{1.0, 0.0};
+        __syncthreads();
+    }
+    for (int e = t; e < n * n; e += nt) {
+        const int j = e / n, i = e - j * n;   // B row j, column i
+        B[e] = i >= j ? zscale(zconj(X[(int64_t)i * n + j]), dsc[j]) : Z{0.0, 0.0};
     }
     if (t == 0) *info = 0;
 }
@@ -297,8 +329,8 @@ inline int grid_for(int64_t total) {
 
 void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, G, n, shift, B,
-                       work, info);
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, G, n, shift, B, work,
+                       info);
     check_launch("k_chol_factor");
 }
 
@@ -312,8 +344,69 @@ void hermitise(Z *G, int n, hipStream_t s) {
 
 // A (overwritten) -> w ascending, Y eigenvectors.  work: 3 n^2 complex.
 // hwork: 2 doubles of pinned host memory for the convergence test.
+JacobiGraphs::~JacobiGraphs() {
+    // A replay may still be queued (an error unwound the solve).
+    if (!entries.empty()) (void)hipStreamSynchronize(used);
+    for (auto &e : entries)
+        for (auto x : e.exec)
+            if (x) (void)hipGraphExecDestroy(x);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+namespace {
+
+// One sweep: m - 1 rounds ping-ponging (A, V) <-> (A2, V2), then the
+// off-diagonal norm of the result.
+void launch_sweep(Z *A, Z *A2, Z *V, Z *V2, int n, int m, int grid, double *dnorm,
+                  hipStream_t s) {
+    for (int r = 0; r < m - 1; ++r) {
+        hipLaunchKernelGGL(k_jacobi_round, dim3(grid), dim3(256), 0, s, A, A2, V, V2, n, m, r);
+        std::swap(A, A2);
+        std::swap(V, V2);
+    }
+    check_launch("k_jacobi_round");
+    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, A, n, dnorm);
+    check_launch("k_offnorm");
+}
+
+// The two captured sweeps for this order and these buffers (parity 0 starts
+// from (A, V), parity 1 from (A2, V2)); captured on first use.
+const hipGraphExec_t *sweep_graphs(JacobiGraphs &g, Z *A, Z *A2, Z *V, Z *V2, int n, int m,
+                                   int grid, double *dnorm, Z *work) {
+    for (auto &e : g.entries)
+        if (e.n == n && e.A == A && e.work == work) return e.exec;
+    if (!g.cap) CHASE_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+    JacobiGraphs::Entry e{n, A, work, {nullptr, nullptr}};
+    for (int par = 0; par < 2; ++par) {
+        hipGraph_t gr = nullptr;
+        CHASE_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+        try {
+            if (par == 0) launch_sweep(A, A2, V, V2, n, m, grid, dnorm, g.cap);
+            else launch_sweep(A2, A, V2, V, n, m, grid, dnorm, g.cap);
+        } catch (...) {
+            (void)hipStreamEndCapture(g.cap, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            for (auto x : e.exec)
+                if (x) (void)hipGraphExecDestroy(x);
+            throw;
+        }
+        CHASE_HIP(hipStreamEndCapture(g.cap, &gr));
+        const hipError_t ie = hipGraphInstantiate(&e.exec[par], gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ie != hipSuccess) {
+            for (auto x : e.exec)
+                if (x) (void)hipGraphExecDestroy(x);
+            throw Error(3, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
+    }
+    g.entries.push_back(e);
+    return g.entries.back().exec;
+}
+
+}  // namespace
+
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
-                hipStream_t s) {
+                hipStream_t s, JacobiGraphs *graphs) {
     Z *A2 = work;
     Z *V = work + (size_t)n * n;
     Z *V2 = work + (size_t)2 * n * n;
@@ -325,17 +418,19 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
         const int h = m / 2;
         const int grid = grid_for((int64_t)h * h + (int64_t)n * h);
         double *dnorm = reinterpret_cast<double *>(Y);   // Y is free until the end
+        const hipGraphExec_t *ex =
+            graphs ? sweep_graphs(*graphs, A, A2, V, V2, n, m, grid, dnorm, work) : nullptr;
         double prev = 1e300;
         for (int sweep = 0; sweep < 30; ++sweep) {
-            for (int r = 0; r < m - 1; ++r) {
-                hipLaunchKernelGGL(k_jacobi_round, dim3(grid), dim3(256), 0, s, A,
-                                   A2, V, V2, n, m, r);
-                std::swap(A, A2);
-                std::swap(V, V2);
+            // m - 1 (odd) rounds: each sweep leaves the result in the other
+            // buffer of the pair, so consecutive sweeps alternate parity.
+            if (ex) {
+                graphs->used = s;
+                CHASE_HIP(hipGraphLaunch(ex[sweep & 1], s));
             }
-            check_launch("k_jacobi_round");
-            hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, A, n, dnorm);
-            check_launch("k_offnorm");
+            else launch_sweep(A, A2, V, V2, n, m, grid, dnorm, s);
+            std::swap(A, A2);
+            std::swap(V, V2);
             CHASE_HIP(hipMemcpyAsync(hwork, dnorm, 2 * sizeof(double),
                                      hipMemcpyDeviceToHost, s));
             CHASE_HIP(hipStreamSynchronize(s));

@@ -340,6 +340,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     std::memset(&R.info, 0, sizeof(R.info));
     chase_info &info = R.info;
     Events E;
+    JacobiGraphs jgraphs;
     std::vector<hipEvent_t> prof, prof32, profx;
     std::vector<int> profx_cols;
     std::vector<hipEvent_t> *profp = o.profile ? &prof : nullptr;
@@ -414,6 +415,9 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     CHASE_HIP(hipStreamSynchronize(s));
     info.t_lanczos = elapsed(l0, l1);
     info.matvecs_total += (int64_t)k * r;
+    const double Nd = (double)N;
+    info.lanczos_flops = 8.0 * Nd * Nd * r * k;
+    info.lanczos_bytes = (double)k * (16.0 * Nd * Nd + 112.0 * Nd * r);
     for (int i = 0; i < k * r; ++i)
         if (!std::isfinite(h_al[i]) || !std::isfinite(h_be[i]))
             throw Error(CHASE_ENONFINITE, "H contains NaN or Inf (seen by Lanczos)");
@@ -466,11 +470,17 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         if (!refine && ne < N && e_half > 1e-14 * std::max(1.0, std::fabs(beta))) {
             // Active columns: the FP32 group first, each group by degree.
             if (n32 > 0) {
+                info.filter_bytes += (double)deg[L + n32 - 1] * 8.0 * Nd * Nd + 48.0 * Nd * n32;
+                for (int j = L; j < L + n32; ++j) info.filter_bytes += 24.0 * Nd * deg[j];
                 z2c_block(V + L, ne, Vc, n32, N, n32, s);
                 filter32_block(Hc, N, Vc, Bc, n32, n32, deg.data() + L, mu1, alpha,
                                beta, fpart32, s, prof32p);
                 c2z_block(Vc, n32, V + L, ne, N, n32, s);
                 for (int j = L; j < L + n32; ++j) info.matvecs_filter_fp32 += deg[j];
+            }
+            if (n - n32 > 0) {
+                info.filter_bytes += (double)deg[ne - 1] * 16.0 * Nd * Nd;
+                for (int j = L + n32; j < ne; ++j) info.filter_bytes += 48.0 * Nd * deg[j];
             }
             if (p.sink)
                 p.sink->run(filter_steps(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne,
@@ -490,7 +500,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         gemm_other(Q, ne, W + L, ne, n);
         gram(Q, ne, W + L, ne, N, n, n, G, n, gpart, s);
         hermitise(G, n, s);
-        jacobi_eig(G, n, theta, Y, jwork, h_jac, s);
+        jacobi_eig(G, n, theta, Y, jwork, h_jac, s, o.graphs ? &jgraphs : nullptr);
         tsmm(Q, ne, Y, n, N, n, n, 1.0, nullptr, 0, 0.0, B1 + L, ne, s);
         CHASE_HIP(hipEventRecord(ev[3], s));
         tsmm(W + L, ne, Y, n, N, n, n, 1.0, nullptr, 0, 0.0, T + L, ne, s);
@@ -500,6 +510,16 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         CHASE_HIP(hipMemcpyAsync(h_th, theta, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipMemcpyAsync(h_res, resid, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipStreamSynchronize(s));
+        {
+            const double nd = n, Ld = L;
+            info.qr_flops += 32.0 * Nd * Ld * nd + 48.0 * Nd * nd * nd;
+            info.qr_bytes += (L > 0 ? 2.0 * (16.0 * Nd * Ld + 32.0 * Nd * nd) : 0.0) +
+                             144.0 * Nd * nd;
+            info.rr_flops += 8.0 * Nd * Nd * nd + 16.0 * Nd * nd * nd;
+            info.rr_bytes += 16.0 * Nd * Nd + 96.0 * Nd * nd;
+            info.resid_flops += 8.0 * Nd * nd * nd + 8.0 * Nd * nd;
+            info.resid_bytes += 96.0 * Nd * nd;
+        }
         info.t_filter += elapsed(ev[0], ev[1]);
         info.t_qr += elapsed(ev[1], ev[2]);
         info.t_rr += elapsed(ev[2], ev[3]);

@@ -130,7 +130,10 @@ def test_lanczos_vs_oracle():
 
 
 @pytest.mark.parametrize("N,n,nlocked,graded", [(1000, 40, 0, False), (777, 33, 0, True),
-                                                 (1200, 50, 17, False), (64, 64, 0, False)])
+                                                 (1200, 50, 17, False), (64, 64, 0, False),
+                                                 (3000, 400, 100, False), (1100, 1024, 0, False),
+                                                 (2000, 180, 0, True), (2000, 181, 0, False),
+                                                 (500, 2, 0, False), (500, 1, 0, False)])
 def test_qr_vs_oracle(N, n, nlocked, graded):
     torch_cuda()
     V = synth.random_block(N, n, seed=N + n)
