@@ -72,8 +72,9 @@ def counter_values(d, match, counter):
 
 
 def _short(name):
-    # 'void ns::k_filter<9, 0, false>(args...)' -> 'k_filter<9, 0, false>'
-    head = name.split("(")[0]
+    # 'void ns::(anonymous namespace)::k_filter<9, 0, false>(args...)'
+    #   -> 'k_filter<9, 0, false>'
+    head = name.replace("(anonymous namespace)", "anon").split("(")[0]
     return head.replace("void ", "").split("::")[-1]
 
 
