@@ -3,10 +3,15 @@
     python -m paper_2006_08498_amd.profsum stats DIR [--match SUBSTR]
     python -m paper_2006_08498_amd.profsum traffic --fetch D --write D \
         --copy-fetch D --copy-write D --copy-bytes B [--match SUBSTR] [--workload W]
+    python -m paper_2006_08498_amd.profsum counters DIR [--match SUBSTR]
 
 `stats` prints the rows of the kernel-statistics CSV under DIR (from
 `rocprofv3 --kernel-trace --stats --output-format csv`) whose kernel name
 contains SUBSTR, plus their call-weighted average duration.
+
+`counters` prints, per kernel, the mean per dispatch of every counter of
+a `--pmc` run (for instance MfmaUtil, the percentage of cycles the MFMA
+units were busy).
 
 `traffic` turns two counter runs (`--pmc FETCH_SIZE`, then `--pmc
 WRITE_SIZE`, KiB per dispatch) into HBM bytes per launch.  Each counter is
@@ -131,6 +136,24 @@ def cmd_traffic(a):
     print("traffic-record: " + json.dumps(rec))
 
 
+def cmd_counters(a):
+    """Mean per dispatch of every counter in the run, per kernel width."""
+    names = collections.defaultdict(dict)
+    for f in _csvs(a.dir, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            if a.match in r["Kernel_Name"]:
+                d = names[_short(r["Kernel_Name"])].setdefault(r["Counter_Name"], [])
+                d.append(float(r["Counter_Value"]))
+    counters = sorted({c for d in names.values() for c in d})
+    print("| kernel | dispatches | " + " | ".join(counters) + " |")
+    print("|---|---:|" + "---:|" * len(counters))
+    for k in sorted(names):
+        d = names[k]
+        nd = max(len(v) for v in d.values())
+        cells = [f"{sum(d[c]) / len(d[c]):.4g}" if c in d else "" for c in counters]
+        print(f"| {k} | {nd} | " + " | ".join(cells) + " |")
+
+
 def read_record(path):
     """The traffic record of a committed profile summary, or None."""
     try:
@@ -155,8 +178,11 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--match", default="k_filter<")
     t.add_argument("--workload", default="planted24k")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--match", default="k_filter<")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
