@@ -288,6 +288,10 @@ def main():
     ap.add_argument("--serve-solo-baseline", action="store_true",
                     help="serve128: also time every request alone, one after another")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", type=lambda t: [int(x) for x in t.split(",") if x != ""],
+                    default=None,
+                    help="comma-separated generator seeds (e.g. 0,1,2,3,4): time each, "
+                         "report each and their median as value")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--h-cache", default="",
@@ -357,6 +361,24 @@ def main():
                                args.switch_tol, args.graphs)
     chk = check_result(H, r, lam, w["tol"])
     log(f"check: {chk}")
+    per_seed = None
+    if args.seeds:
+        # The same workload over several generator seeds: each seed's time
+        # per solve and checks; `value` becomes their median.
+        per_seed = [{"seed": args.seed, "value": per, "iterations": r.info["iterations"],
+                     "check": chk}]
+        for sd in args.seeds:
+            if sd == args.seed:
+                continue
+            del H
+            H, lam_s = make_matrix(w, sd)
+            torch.cuda.synchronize()
+            inf_s, per_s, r_s = run_solves(H, w, ws, precision, args.steps, args.warmup, sd,
+                                           args.switch_tol, args.graphs)
+            per_seed.append({"seed": sd, "value": per_s, "iterations": r_s.info["iterations"],
+                             "check": check_result(H, r_s, lam_s, w["tol"])})
+            log(f"seed {sd}: {per_s:.4f} s per solve")
+        per = float(np.median([e["value"] for e in per_seed]))
 
     def sums(infos):
         keys = ("filter_flops", "t_filter_kernels", "filter_launches", "t_filter",
@@ -452,6 +474,7 @@ def main():
         "phases_s": phases,
         "phase_roofline": phase_roof,
         "check": chk,
+        **({"per_seed": per_seed} if per_seed else {}),
         "roofline": roof,
     }
     if precision == chase.CHASE_MIXED and not args.no_fp64_reference:
