@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 namespace chase {
@@ -47,7 +49,38 @@ struct FilterPlan {
     int splits;   // K splits (1 = epilogue fused)
     int kchunk;   // K rows per split (multiple of 4)
 };
+// Tile plan of one GEMM of at most kMaxTileCols columns.
+constexpr int kMaxTileCols = 160;   // 10 tiles of 16 columns per wave
 FilterPlan filter_plan(int64_t N, int n);
+// Wider blocks run as balanced chunks of whole 16-column tiles, each its
+// own GEMM (at most kMaxTileCols columns), so only the last 16-column tile
+// of the block carries padding.  Returns (first column, columns) pairs.
+inline std::vector<std::pair<int, int>> column_chunks(int n) {
+    std::vector<std::pair<int, int>> out;
+    if (n <= 0) return out;
+    const int tiles = (n + 15) / 16;
+    const int maxt = kMaxTileCols / 16;
+    const int nc = (tiles + maxt - 1) / maxt;
+    int t0 = 0;
+    for (int i = 0; i < nc; ++i) {
+        const int w = tiles / nc + (i < tiles % nc ? 1 : 0);
+        const int c0 = 16 * t0, c1 = std::min(n, 16 * (t0 + w));
+        out.emplace_back(c0, c1 - c0);
+        t0 += w;
+    }
+    return out;
+}
+// The launches of a filter GEMM of n columns, in order: one launch when
+// the columns fit one tile block or split evenly into blocks of equal
+// width (several column blocks in one grid), otherwise one launch per
+// balanced chunk.  Columns [c0, c0 + n) with tile plan p.
+struct FilterPiece {
+    int c0, n;
+    FilterPlan p;
+};
+std::vector<FilterPiece> filter_pieces(int64_t N, int n);
+// Split-K scratch (elements) for a filter GEMM of n columns: the largest
+// piece's need, pieces running one after another.
 size_t filter_partial_elems(int64_t N, int n);
 void filter_gemm(const Z *H, int64_t ldh, int64_t N, const Z *Y, int64_t ldy,
                  const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
@@ -70,14 +103,15 @@ struct FilterCall {
 };
 // Several independent filter GEMMs (different H, sizes and buffers) in as
 // few launches as possible: one MFMA launch per distinct tile width and one
-// reduction launch for the split ones.  Each call keeps the tile plan
-// filter_plan(N, n) it would have alone, so its result is bitwise the same
-// as a filter_gemm call.
+// reduction launch for the split ones (per round of column chunks).  Each
+// call keeps the column chunks and tile plans filter_gemm gives it alone,
+// so its result is bitwise the same as a filter_gemm call.
 void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s);
 
 // FP32 filter GEMM on the complex64 shadow Hc (mixed precision), same
 // contract as filter_gemm; partials: filter32_partial_elems(N, n) complex64.
 FilterPlan filter32_plan(int64_t N, int n);
+std::vector<FilterPiece> filter32_pieces(int64_t N, int n);
 size_t filter32_partial_elems(int64_t N, int n);
 void filter32_gemm(const C *H, int64_t ldh, int64_t N, const C *Y, int64_t ldy,
                    const C *X, int64_t ldx, C *W, int64_t ldw, int n, float a,

@@ -96,26 +96,25 @@ int reduce_blocks(int64_t N, int n) {
     return (int)std::min<int64_t>(((int64_t)N * n + 255) / 256, 4096);
 }
 
+void filter_group_round(const std::vector<std::pair<FilterCall, FilterPlan>> &rd,
+                        hipStream_t s);
+
 }  // namespace
 
-FilterPlan filter_plan(int64_t N, int n) {
-    FilterPlan p{};
-    const int nb16 = (n + 15) / 16;
-    if (nb16 <= 10) {
-        p.cb = 1;
-        p.wn = nb16;
-    } else {
-        p.cb = (nb16 + 9) / 10;
-        p.wn = (nb16 + p.cb - 1) / p.cb;
-    }
-    p.rb = (int)((N + 63) / 64);
-    // K splits balance the workgroups over the 256 CUs.  Resident
-    // workgroups per CU = waves per SIMD of the tile's register budget
-    // (hipcc resource usage for gfx950); a round of `slots` workgroups runs
-    // concurrently, and a workgroup's time falls as 1/splits.  Splitting
-    // costs a partial-sum pass (2 * splits * N * n * 16 bytes), charged at
-    // 2% per split.
+namespace {
+
+// Tile plan for cb column blocks of wn 16-column tiles over N rows.  K
+// splits balance the workgroups over the 256 CUs: resident workgroups per
+// CU = waves per SIMD of the tile's register budget (hipcc resource usage
+// for gfx950); a round of `slots` workgroups runs concurrently, and a
+// workgroup's time falls as 1/splits.  Splitting costs a partial-sum pass
+// (2 * splits * N * n * 16 bytes), charged at 2% per split.
+FilterPlan plan_blocks(int64_t N, int wn, int cb) {
     static const int occ[11] = {0, 3, 2, 2, 2, 2, 2, 1, 1, 1, 1};
+    FilterPlan p{};
+    p.wn = wn;
+    p.cb = cb;
+    p.rb = (int)((N + 63) / 64);
     const int64_t slots = 256 * (int64_t)occ[p.wn];
     const int64_t units = (int64_t)p.rb * p.cb;
     double best = 1e300;
@@ -136,9 +135,32 @@ FilterPlan filter_plan(int64_t N, int n) {
     return p;
 }
 
+}  // namespace
+
+FilterPlan filter_plan(int64_t N, int n) {
+    if (n < 1 || n > kMaxTileCols) throw Error(7, "filter_plan: bad column count");
+    return plan_blocks(N, (n + 15) / 16, 1);
+}
+
+std::vector<FilterPiece> filter_pieces(int64_t N, int n) {
+    std::vector<FilterPiece> out;
+    if (n <= 0) return out;
+    const int tiles = (n + 15) / 16, maxt = kMaxTileCols / 16;
+    const int nc = (tiles + maxt - 1) / maxt;
+    if (tiles % nc == 0) {
+        out.push_back(FilterPiece{0, n, plan_blocks(N, tiles / nc, nc)});
+        return out;
+    }
+    for (const auto &ch : column_chunks(n))
+        out.push_back(FilterPiece{ch.first, ch.second, filter_plan(N, ch.second)});
+    return out;
+}
+
 size_t filter_partial_elems(int64_t N, int n) {
-    const FilterPlan p = filter_plan(N, n);
-    return p.splits > 1 ? (size_t)p.splits * (size_t)N * (size_t)n : 0;
+    size_t e = 0;
+    for (const FilterPiece &pc : filter_pieces(N, n))
+        if (pc.p.splits > 1) e = std::max(e, (size_t)pc.p.splits * (size_t)N * (size_t)pc.n);
+    return e;
 }
 
 void filter_gemm(const Z *H, int64_t ldh, int64_t N64, const Z *Y, int64_t ldy,
@@ -147,37 +169,68 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N64, const Z *Y, int64_t ldy,
                  hipEvent_t after_mfma) {
     if (n <= 0 || N64 <= 0) return;
     const int N = (int)N64;
-    const FilterPlan p = filter_plan(N64, n);
-    if (p.splits > 1 && !part) throw Error(7, "filter_gemm: missing partials");
-    switch (p.wn) {
+    const auto pieces = filter_pieces(N64, n);
+    for (size_t i = 0; i < pieces.size(); ++i) {
+        const FilterPlan &p = pieces[i].p;
+        const int c0 = pieces[i].c0, nc = pieces[i].n;
+        const Z *Yc = Y + c0, *Xc = X ? X + c0 : nullptr;
+        Z *Wc = W + c0;
+        if (p.splits > 1 && !part) throw Error(7, "filter_gemm: missing partials");
+        switch (p.wn) {
 #define CASE(w) \
-    case w: launch_wn<w>(p, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, part, s); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    case w: launch_wn<w>(p, H, ldh, N, Yc, ldy, Xc, ldx, Wc, ldw, nc, a, b, g, part, s); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-        case 9:
-        case 10:
-            launch_filter_wide(p, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, part, s);
-            break;
-        default: throw Error(7, "filter_gemm: bad tile width");
-    }
-    check_launch("k_filter");
-    if (after_mfma) CHASE_HIP(hipEventRecord(after_mfma, s));
-    if (p.splits > 1) {
-        hipLaunchKernelGGL(k_filter_reduce, dim3(reduce_blocks(N, n)), dim3(256), 0, s, part,
-                           p.splits, N, n, Y, ldy, X, ldx, W, ldw, a, b, g);
-        check_launch("k_filter_reduce");
+            case 9:
+            case 10:
+                launch_filter_wide(p, H, ldh, N, Yc, ldy, Xc, ldx, Wc, ldw, nc, a, b, g, part,
+                                   s);
+                break;
+            default: throw Error(7, "filter_gemm: bad tile width");
+        }
+        check_launch("k_filter");
+        if (after_mfma && i + 1 == pieces.size()) CHASE_HIP(hipEventRecord(after_mfma, s));
+        if (p.splits > 1) {
+            hipLaunchKernelGGL(k_filter_reduce, dim3(reduce_blocks(N, nc)), dim3(256), 0, s,
+                               part, p.splits, N, nc, Yc, ldy, Xc, ldx, Wc, ldw, a, b, g);
+            check_launch("k_filter_reduce");
+        }
     }
 }
 
 void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s) {
-    std::vector<FilterPlan> plan;
-    std::vector<FilterCall> live;
+    // Round r holds piece r of every call (see filter_pieces), so each
+    // call's split-K scratch is used by one piece at a time, in the order
+    // filter_gemm uses it.
+    std::vector<std::vector<std::pair<FilterCall, FilterPlan>>> rounds;
     for (int i = 0; i < count; ++i) {
         if (calls[i].n <= 0 || calls[i].N <= 0) continue;
-        const FilterPlan p = filter_plan(calls[i].N, calls[i].n);
-        if (p.splits > 1 && !calls[i].part) throw Error(7, "filter_gemm_group: missing partials");
-        plan.push_back(p);
-        live.push_back(calls[i]);
+        const auto pieces = filter_pieces(calls[i].N, calls[i].n);
+        if (rounds.size() < pieces.size()) rounds.resize(pieces.size());
+        for (size_t r = 0; r < pieces.size(); ++r) {
+            FilterCall c = calls[i];
+            c.Y += pieces[r].c0;
+            if (c.X) c.X += pieces[r].c0;
+            c.W += pieces[r].c0;
+            c.n = pieces[r].n;
+            rounds[r].emplace_back(c, pieces[r].p);
+        }
+    }
+    for (const auto &rd : rounds) filter_group_round(rd, s);
+}
+
+namespace {
+// One grouped launch per tile width present, then the split GEMMs'
+// reductions.
+void filter_group_round(const std::vector<std::pair<FilterCall, FilterPlan>> &rd,
+                        hipStream_t s) {
+    std::vector<FilterPlan> plan;
+    std::vector<FilterCall> live;
+    for (const auto &cp : rd) {
+        if (cp.second.splits > 1 && !cp.first.part)
+            throw Error(7, "filter_gemm_group: missing partials");
+        live.push_back(cp.first);
+        plan.push_back(cp.second);
     }
     // MFMA launches, one per tile width present (chunks of kMaxGroup).
     for (int wn = 1; wn <= 10; ++wn) {
@@ -220,5 +273,7 @@ void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s) {
         check_launch("k_filter_reduce_group");
     }
 }
+
+}  // namespace
 
 }  // namespace chase

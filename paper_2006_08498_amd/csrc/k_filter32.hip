@@ -234,19 +234,15 @@ inline int grid_for(int64_t total) {
 
 }  // namespace
 
-FilterPlan filter32_plan(int64_t N, int n) {
-    FilterPlan p{};
-    const int nb16 = (n + 15) / 16;
-    if (nb16 <= 10) {
-        p.cb = 1;
-        p.wn = nb16;
-    } else {
-        p.cb = (nb16 + 9) / 10;
-        p.wn = (nb16 + p.cb - 1) / p.cb;
-    }
-    p.rb = (int)((N + 63) / 64);
-    // Resident workgroups per CU from the FP32 kernels' register budgets.
+namespace {
+
+// As the FP64 plan, with the FP32 kernels' register budgets.
+FilterPlan plan32_blocks(int64_t N, int wn, int cb) {
     static const int occ[11] = {0, 4, 3, 2, 2, 2, 1, 2, 1, 1, 1};
+    FilterPlan p{};
+    p.wn = wn;
+    p.cb = cb;
+    p.rb = (int)((N + 63) / 64);
     const int64_t slots = 256 * (int64_t)occ[p.wn];
     const int64_t units = (int64_t)p.rb * p.cb;
     double best = 1e300;
@@ -267,9 +263,32 @@ FilterPlan filter32_plan(int64_t N, int n) {
     return p;
 }
 
+}  // namespace
+
+FilterPlan filter32_plan(int64_t N, int n) {
+    if (n < 1 || n > kMaxTileCols) throw Error(7, "filter32_plan: bad column count");
+    return plan32_blocks(N, (n + 15) / 16, 1);
+}
+
+std::vector<FilterPiece> filter32_pieces(int64_t N, int n) {
+    std::vector<FilterPiece> out;
+    if (n <= 0) return out;
+    const int tiles = (n + 15) / 16, maxt = kMaxTileCols / 16;
+    const int nc = (tiles + maxt - 1) / maxt;
+    if (tiles % nc == 0) {
+        out.push_back(FilterPiece{0, n, plan32_blocks(N, tiles / nc, nc)});
+        return out;
+    }
+    for (const auto &ch : column_chunks(n))
+        out.push_back(FilterPiece{ch.first, ch.second, filter32_plan(N, ch.second)});
+    return out;
+}
+
 size_t filter32_partial_elems(int64_t N, int n) {
-    const FilterPlan p = filter32_plan(N, n);
-    return p.splits > 1 ? (size_t)p.splits * (size_t)N * (size_t)n : 0;
+    size_t e = 0;
+    for (const FilterPiece &pc : filter32_pieces(N, n))
+        if (pc.p.splits > 1) e = std::max(e, (size_t)pc.p.splits * (size_t)N * (size_t)pc.n);
+    return e;
 }
 
 void filter32_gemm(const C *H, int64_t ldh, int64_t N64, const C *Y, int64_t ldy,
@@ -277,22 +296,29 @@ void filter32_gemm(const C *H, int64_t ldh, int64_t N64, const C *Y, int64_t ldy
                    float b, float g, C *part, hipStream_t s, hipEvent_t after_mfma) {
     if (n <= 0 || N64 <= 0) return;
     const int N = (int)N64;
-    const FilterPlan p = filter32_plan(N64, n);
-    if (p.splits > 1 && !part) throw Error(7, "filter32_gemm: missing partials");
-    switch (p.wn) {
-#define CASE(w) case w: launch32<w>(p, H, ldh, N, Y, ldy, X, ldx, W, ldw, n, a, b, g, part, s); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+    const auto pieces = filter32_pieces(N64, n);
+    for (size_t i = 0; i < pieces.size(); ++i) {
+        const FilterPlan &p = pieces[i].p;
+        const int c0 = pieces[i].c0, nc = pieces[i].n;
+        const C *Yc = Y + c0, *Xc = X ? X + c0 : nullptr;
+        C *Wc = W + c0;
+        if (p.splits > 1 && !part) throw Error(7, "filter32_gemm: missing partials");
+        switch (p.wn) {
+#define CASE(w) case w: launch32<w>(p, H, ldh, N, Yc, ldy, Xc, ldx, Wc, ldw, nc, a, b, g, part, s); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
-        default: throw Error(7, "filter32_gemm: bad tile width");
-    }
-    check_launch("k_filter32");
-    if (after_mfma) CHASE_HIP(hipEventRecord(after_mfma, s));
-    if (p.splits > 1) {
-        const int64_t total = (int64_t)N * n;
-        hipLaunchKernelGGL(k_filter32_reduce, dim3((int)std::min<int64_t>((total + 255) / 256, 4096)),
-                           dim3(256), 0, s, part, p.splits, N, n, Y, ldy, X, ldx, W,
-                           ldw, a, b, g);
-        check_launch("k_filter32_reduce");
+            default: throw Error(7, "filter32_gemm: bad tile width");
+        }
+        check_launch("k_filter32");
+        if (after_mfma && i + 1 == pieces.size()) CHASE_HIP(hipEventRecord(after_mfma, s));
+        if (p.splits > 1) {
+            const int64_t total = (int64_t)N * nc;
+            hipLaunchKernelGGL(k_filter32_reduce,
+                               dim3((int)std::min<int64_t>((total + 255) / 256, 4096)),
+                               dim3(256), 0, s, part, p.splits, N, nc, Yc, ldy, Xc, ldx, Wc,
+                               ldw, a, b, g);
+            check_launch("k_filter32_reduce");
+        }
     }
 }
 

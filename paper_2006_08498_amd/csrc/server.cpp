@@ -229,6 +229,8 @@ struct chase_server {
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
+    hipStream_t copy_stream = nullptr;   // poll's result copies (non-blocking)
+    std::mutex copy_mu;
     int device = 0;
     std::unique_ptr<Broker> broker;   // CHASE_SERVER_FUSE_FILTER
 };
@@ -277,7 +279,11 @@ void run_one(chase_server *s, Request *r, int slot) {
             }
             H = reinterpret_cast<const Z *>(dH);
         }
-        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts, s->broker.get()};
+        // No graph capture in worker threads: a capture in progress would make
+        // the callers' legacy-default-stream work fail meanwhile.
+        chase_opts ro = r->opts;
+        ro.graphs = 0;
+        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, ro, s->broker.get()};
         Result R = solve(p, dW, reinterpret_cast<Z *>(dV), r->N, st);
         r->eigvals = std::move(R.eigvals);
         r->resid = std::move(R.resid);
@@ -392,6 +398,7 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
             CHASE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             s->streams.push_back(st);
         }
+        CHASE_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
         if (flags & CHASE_SERVER_FUSE_FILTER) s->broker = std::make_unique<Broker>(s->device);
         for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker, s, i);
         return s;
@@ -462,8 +469,11 @@ int chase_server_poll(chase_server *s, uint64_t ticket, double *h_eigvals,
     try {
         if (r->dV) {
             if (!dV || ldv < r->N) return srv_fail(CHASE_EINVAL, "dV is NULL or ldv < N");
-            CHASE_HIP(hipMemcpy2D(dV, (size_t)ldv * sizeof(Z), r->dV, (size_t)r->N * sizeof(Z),
-                                  (size_t)r->N * sizeof(Z), r->nev, hipMemcpyDeviceToDevice));
+            std::lock_guard<std::mutex> lk(s->copy_mu);
+            CHASE_HIP(hipMemcpy2DAsync(dV, (size_t)ldv * sizeof(Z), r->dV,
+                                       (size_t)r->N * sizeof(Z), (size_t)r->N * sizeof(Z),
+                                       r->nev, hipMemcpyDeviceToDevice, s->copy_stream));
+            CHASE_HIP(hipStreamSynchronize(s->copy_stream));
         }
         if (h_eigvals && !r->eigvals.empty())
             std::copy(r->eigvals.begin(), r->eigvals.end(), h_eigvals);
@@ -532,6 +542,7 @@ void chase_server_destroy(chase_server *s) {
     for (auto &kv : s->reqs)
         if (kv.second->dV) (void)hipFree(kv.second->dV);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     delete s;
 }
 
