@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <numeric>
 
 namespace chase {
@@ -288,6 +289,24 @@ struct Events {
     }
 };
 
+// On an error, waits for the stream before the buffers declared ahead of
+// it (pinned host staging in particular) are released: a copy into them may
+// still be in flight.
+struct SyncOnUnwind {
+    hipStream_t s;
+    int pending = std::uncaught_exceptions();
+    ~SyncOnUnwind() {
+        if (std::uncaught_exceptions() > pending) (void)hipStreamSynchronize(s);
+    }
+};
+
+// Profile events still held when the solve ends early.
+struct EventList : std::vector<hipEvent_t> {
+    ~EventList() {
+        for (auto e : *this) (void)hipEventDestroy(e);
+    }
+};
+
 double elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     CHASE_HIP(hipEventElapsedTime(&ms, a, b));
@@ -335,13 +354,14 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     double *h_th = h_be + (size_t)k * r, *h_res = h_th + ne;
     double *h_misc = h_res + ne;   // 4 ints of QR info + Jacobi norms
     double *h_jac = h_misc + 4;
+    SyncOnUnwind unwind_sync{s};
 
     Result R{};
     std::memset(&R.info, 0, sizeof(R.info));
     chase_info &info = R.info;
     Events E;
     JacobiGraphs jgraphs;
-    std::vector<hipEvent_t> prof, prof32, profx;
+    EventList prof, prof32, profx;
     std::vector<int> profx_cols;
     std::vector<hipEvent_t> *profp = o.profile ? &prof : nullptr;
     std::vector<hipEvent_t> *prof32p = o.profile ? &prof32 : nullptr;
