@@ -227,3 +227,14 @@ def test_graph_replayed_jacobi_sweeps_match_direct_launches(N, nev, nex, seed):
         assert np.array_equal(host(g.V), host(r.V))
         assert g.info["iterations"] == r.info["iterations"]
     _check_against_oracle(H, g, nev)
+
+
+def test_largest_subspace_1024():
+    """nev + nex at the ABI's maximum (1024): Jacobi at order 1024, filter
+    products split into column pieces, the Cholesky factor at full size."""
+    torch_cuda()
+    N, nev, nex = 2600, 700, 324
+    H = synth.dk_matrix(N, seed=21)
+    r = chase.solve(dev_colmajor(H), nev, nex, 1e-10, 20)
+    assert r.status == chase.CHASE_OK
+    _check_against_oracle(H, r, nev)
