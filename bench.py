@@ -81,7 +81,8 @@ def run_serve(args):
         return fill
 
     precision = chase.CHASE_MIXED if args.serve_precision == "mixed" else chase.CHASE_FP64
-    srv = chase.Server(budget_bytes=0, slots=args.slots, fuse=args.fuse)
+    srv = chase.Server(budget_bytes=0, slots=args.slots, fuse=args.fuse,
+                       shortest_first=args.policy == "sjf")
     log(f"serving {len(sched)} requests over {sched[-1]['t']:.1f} s with "
         f"{args.slots} slots")
     pending = {}
@@ -139,7 +140,7 @@ def run_serve(args):
         "data": "synthetic",
         "config": {"workload": "serve128: 128 requests, Poisson 4/s, N in {4k..20k} D+K, "
                                "nev in [30,150], nex=0.4 nev, tol 1e-10, degree<=20",
-                   "precision": args.serve_precision,
+                   "precision": args.serve_precision, "admission": args.policy,
                    "slots": args.slots, "fuse_filter": bool(args.fuse),
                    "parallelism": "1 GPU"},
         "p50_s": p50, "p99_s": p99,
@@ -283,6 +284,9 @@ def main():
     ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
     ap.add_argument("--fuse", type=int, default=0,
                     help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
+    ap.add_argument("--policy", choices=("fifo", "sjf"), default="fifo",
+                    help="serve128: admission in arrival order or shortest estimated work "
+                         "first (with aging)")
     ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64",
                     help="serve128: precision of the served solves")
     ap.add_argument("--serve-solo-baseline", action="store_true",

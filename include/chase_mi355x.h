@@ -362,12 +362,21 @@ enum {
      * per tick holds the next step of every running solve that is in its
      * filter phase (chase_filter_step_group), instead of one launch per
      * step per solve.  Results are bitwise the same either way. */
-    CHASE_SERVER_FUSE_FILTER = 1
+    CHASE_SERVER_FUSE_FILTER = 1,
+    /* Admission order: among the queued requests that fit, the one with
+     * the least estimated work (N^2 (nev + nex)) first, instead of arrival
+     * order; a request that has waited longer than the aging time (30 s by
+     * default, chase_server_set_aging) is admitted first, in arrival order,
+     * so large requests are not starved.  Lowers the median latency of an
+     * overloaded server at the cost of its largest requests. */
+    CHASE_SERVER_SHORTEST_FIRST = 2
 };
 
 /* hbm_budget_bytes: device memory the server may allocate (0 = free memory
- * minus a reserve); max_slots: concurrent solves (1..64); flags: 0 or
- * CHASE_SERVER_FUSE_FILTER.  NULL on failure (chase_server_last_error()). */
+ * minus a reserve); max_slots: concurrent solves (1..64); flags: a
+ * combination of CHASE_SERVER_FUSE_FILTER and CHASE_SERVER_SHORTEST_FIRST
+ * (0 = arrival order, no fusion).  NULL on failure
+ * (chase_server_last_error()). */
 chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots,
                                   uint32_t flags);
 
@@ -407,6 +416,10 @@ int chase_server_wait(chase_server *srv, uint64_t ticket, double timeout_s);
 int chase_server_stats(chase_server *srv, size_t *bytes_in_use,
                        size_t *peak_bytes, int32_t *running,
                        int32_t *peak_running, int32_t *queued);
+
+/* With CHASE_SERVER_SHORTEST_FIRST: the wait (seconds, >= 0) after which a
+ * queued request is admitted in arrival order. */
+int chase_server_set_aging(chase_server *srv, double seconds);
 
 /* With CHASE_SERVER_FUSE_FILTER: grouped launches issued so far (ticks)
  * and the filter steps they held; both 0 without fusion. */

@@ -32,6 +32,7 @@ CHASE_EINTERNAL = 7
 CHASE_FP64 = 0
 CHASE_MIXED = 1
 CHASE_SERVER_FUSE_FILTER = 1
+CHASE_SERVER_SHORTEST_FIRST = 2
 
 STATUS_NAMES = {
     CHASE_PENDING: "CHASE_PENDING", CHASE_OK: "CHASE_OK",
@@ -463,6 +464,7 @@ FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes
 
 SIGNATURES.update({
     "chase_server_create": (ctypes.c_void_p, [ctypes.c_size_t, _I32, ctypes.c_uint32]),
+    "chase_server_set_aging": (ctypes.c_int, [_P, _D]),
     "chase_server_fusion_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                                  ctypes.POINTER(ctypes.c_int64)]),
     "chase_server_submit": (ctypes.c_int, [_P, _P, ctypes.c_int, _I64, _I64, _I32, _I32, _D,
@@ -504,13 +506,17 @@ class Server:
     callable fill(ptr, N, ld, stream_ptr) -> int run at admission on the
     slot's stream."""
 
-    def __init__(self, budget_bytes=0, slots=4, fuse=False):
+    def __init__(self, budget_bytes=0, slots=4, fuse=False, shortest_first=False,
+                 aging_s=None):
         L = lib()
-        self._s = L.chase_server_create(int(budget_bytes), int(slots),
-                                        CHASE_SERVER_FUSE_FILTER if fuse else 0)
+        flags = (CHASE_SERVER_FUSE_FILTER if fuse else 0) | \
+                (CHASE_SERVER_SHORTEST_FIRST if shortest_first else 0)
+        self._s = L.chase_server_create(int(budget_bytes), int(slots), flags)
         if not self._s:
             msg = L.chase_server_last_error()
             raise ChaseError(CHASE_EINTERNAL, msg.decode() if msg else "create failed")
+        if aging_s is not None:
+            _check(L.chase_server_set_aging(self._s, float(aging_s)))
         self._keep = {}      # ticket -> objects kept alive (tensors, callbacks)
         self._shape = {}     # ticket -> (N, nev)
 

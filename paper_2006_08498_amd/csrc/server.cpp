@@ -219,6 +219,8 @@ class Broker final : public FilterSink {
 struct chase_server {
     size_t budget = 0;
     int max_slots = 0;
+    uint32_t flags = 0;
+    double aging_s = 30.0;   // CHASE_SERVER_SHORTEST_FIRST: FIFO after this wait
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> pending;
@@ -245,16 +247,36 @@ size_t footprint(const Request &r) {
     return ws + hb + (size_t)r.N * r.nev * sizeof(Z) + 3 * 256;
 }
 
-// First request in arrival order that fits the free memory.
+// Estimated work of a request: the filter's N^2 per column times the
+// subspace size (the per-request iteration count is not known up front).
+double est_work(const Request &r) {
+    return (double)r.N * (double)r.N * (double)(r.nev + r.nex);
+}
+
+// The next request to admit among those that fit the free memory: the
+// first in arrival order, or (CHASE_SERVER_SHORTEST_FIRST) the one with the
+// least estimated work, except that a request waiting longer than aging_s
+// goes first (in arrival order) so that large requests are not starved.
 Request *pick(chase_server *s) {
-    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
-        if ((*it)->footprint + s->in_use <= s->budget) {
-            Request *r = *it;
-            s->pending.erase(it);
-            return r;
-        }
+    auto fits = [&](const Request *r) { return r->footprint + s->in_use <= s->budget; };
+    auto take = [&](std::deque<Request *>::iterator it) {
+        Request *r = *it;
+        s->pending.erase(it);
+        return r;
+    };
+    if (!(s->flags & CHASE_SERVER_SHORTEST_FIRST)) {
+        for (auto it = s->pending.begin(); it != s->pending.end(); ++it)
+            if (fits(*it)) return take(it);
+        return nullptr;
     }
-    return nullptr;
+    const auto now = Clock::now();
+    auto best = s->pending.end();
+    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+        if (!fits(*it)) continue;
+        if (secs(now - (*it)->t_submit) > s->aging_s) return take(it);
+        if (best == s->pending.end() || est_work(**it) < est_work(**best)) best = it;
+    }
+    return best == s->pending.end() ? nullptr : take(best);
 }
 
 void run_one(chase_server *s, Request *r, int slot) {
@@ -379,7 +401,7 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
             g_srv_err = "max_slots must be in [1, 64]";
             return nullptr;
         }
-        if (flags & ~(uint32_t)CHASE_SERVER_FUSE_FILTER) {
+        if (flags & ~(uint32_t)(CHASE_SERVER_FUSE_FILTER | CHASE_SERVER_SHORTEST_FIRST)) {
             g_srv_err = "unknown server flags";
             return nullptr;
         }
@@ -393,6 +415,7 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
         }
         s->budget = hbm_budget_bytes;
         s->max_slots = max_slots;
+        s->flags = flags;
         for (int i = 0; i < max_slots; ++i) {
             hipStream_t st;
             CHASE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -506,6 +529,14 @@ int chase_server_wait(chase_server *s, uint64_t ticket, double timeout_s) {
     if (timeout_s < 0) s->cv_done.wait(lk, done);
     else s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
     return done() ? CHASE_OK : CHASE_PENDING;
+}
+
+int chase_server_set_aging(chase_server *s, double seconds) {
+    if (!s || !(seconds >= 0.0)) return srv_fail(CHASE_EINVAL, "NULL server or negative aging");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->aging_s = seconds;
+    s->cv_work.notify_all();
+    return CHASE_OK;
 }
 
 int chase_server_fusion_stats(chase_server *s, int64_t *ticks, int64_t *steps) {

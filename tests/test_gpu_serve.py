@@ -101,3 +101,30 @@ def test_fill_callback_generates_h_at_admission():
         out = srv.poll(t)
     assert np.array_equal(ref.eigvals, out.eigvals)
     assert np.array_equal(host(ref.V), host(out.V))
+
+
+def test_shortest_first_admission_and_aging():
+    """One slot: after the first admission, shortest-first takes the queued
+    requests by estimated work N^2 (nev + nex); with aging 0 every waiting
+    request counts as aged and the order is arrival order.  Results are
+    those of solo solves either way."""
+    torch_cuda()
+    reqs = [(3000, 30, 12, 41), (2800, 20, 8, 42), (1200, 10, 4, 43), (2000, 16, 6, 44)]
+    mats = [dev_colmajor(synth.dk_matrix(N, seed=s)) for N, _, _, s in reqs]
+    solo = [_solo(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, reqs)]
+    work = [N * N * (nev + nex) for N, nev, nex, _ in reqs]
+    for aging, expect_fifo in ((None, False), (0.0, True)):
+        with chase.Server(slots=1, shortest_first=True, aging_s=aging) as srv:
+            tickets = [srv.submit(H, nev, nex) for H, (N, nev, nex, s) in zip(mats, reqs)]
+            outs = []
+            for t in tickets:
+                assert srv.wait(t, timeout=120.0)
+                outs.append(srv.poll(t))
+        order = sorted(range(len(reqs)), key=lambda i: outs[i].queued_s)
+        if expect_fifo:
+            assert order == list(range(len(reqs)))
+        else:
+            rest = order[1:]
+            assert [work[i] for i in rest] == sorted(work[i] for i in rest)
+        for a, b in zip(solo, outs):
+            assert np.array_equal(a.eigvals, b.eigvals)
