@@ -92,15 +92,12 @@ typedef struct chase_opts {
                                  random start */
     int32_t profile;          /* 1: time every filter launch with HIP events
                                  (fills t_filter_kernels) */
-    int32_t graphs;           /* 1: run each Jacobi sweep of the Rayleigh-Ritz
-                                 eigensolve as one replay of a captured HIP
-                                 graph (captured once per order); 0 (default):
-                                 launch the sweep's kernels one by one.  Same
-                                 results either way.  While a capture is in
-                                 progress, work that other threads of the
-                                 process put on the legacy default stream can
-                                 fail, so use it only where nothing else does;
-                                 the server ignores it. */
+    int32_t graphs;           /* 1 (default): run each Jacobi sweep of the
+                                 Rayleigh-Ritz eigensolve as one launch of a
+                                 HIP graph (built node by node once per order,
+                                 no stream capture); 0: launch the sweep's
+                                 kernels one by one.  Same results either
+                                 way. */
     /* Optional, called on the host thread running the solve (a server's
      * worker thread for served requests) after every subspace iteration with the record so far (iterations, nconv = locked pairs,
      * counters and phase times; alpha/mu1 of that iteration).  A nonzero

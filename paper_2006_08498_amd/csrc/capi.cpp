@@ -118,7 +118,7 @@ void chase_default_opts(chase_opts *o) {
     o->switch_tol = 1e-7;
     o->dV0 = nullptr;
     o->profile = 0;
-    o->graphs = 0;
+    o->graphs = 1;
 }
 
 const char *chase_last_error(void) { return g_err.c_str(); }

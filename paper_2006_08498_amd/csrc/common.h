@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "k_filter_plan.h"
+
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -42,46 +44,7 @@ inline void check_launch(const char *what) {
 // Filter GEMM: W[:, 0:n] = a*H*Y + b*Y + g*X (X may be null when g == 0;
 // W may alias X).  `part` is scratch for split-K partial sums of
 // filter_partial_elems(N, n) elements (may be null if that is 0).
-struct FilterPlan {
-    int wn;       // 16-column blocks per wave (1..10)
-    int cb;       // column blocks of 16*wn columns
-    int rb;       // row blocks of 64 rows
-    int splits;   // K splits (1 = epilogue fused)
-    int kchunk;   // K rows per split (multiple of 4)
-};
-// Tile plan of one GEMM of at most kMaxTileCols columns.
-constexpr int kMaxTileCols = 160;   // 10 tiles of 16 columns per wave
-FilterPlan filter_plan(int64_t N, int n);
-// Wider blocks run as balanced chunks of whole 16-column tiles, each its
-// own GEMM (at most kMaxTileCols columns), so only the last 16-column tile
-// of the block carries padding.  Returns (first column, columns) pairs.
-inline std::vector<std::pair<int, int>> column_chunks(int n) {
-    std::vector<std::pair<int, int>> out;
-    if (n <= 0) return out;
-    const int tiles = (n + 15) / 16;
-    const int maxt = kMaxTileCols / 16;
-    const int nc = (tiles + maxt - 1) / maxt;
-    int t0 = 0;
-    for (int i = 0; i < nc; ++i) {
-        const int w = tiles / nc + (i < tiles % nc ? 1 : 0);
-        const int c0 = 16 * t0, c1 = std::min(n, 16 * (t0 + w));
-        out.emplace_back(c0, c1 - c0);
-        t0 += w;
-    }
-    return out;
-}
-// The launches of a filter GEMM of n columns, in order: one launch when
-// the columns fit one tile block or split evenly into blocks of equal
-// width (several column blocks in one grid), otherwise one launch per
-// balanced chunk.  Columns [c0, c0 + n) with tile plan p.
-struct FilterPiece {
-    int c0, n;
-    FilterPlan p;
-};
-std::vector<FilterPiece> filter_pieces(int64_t N, int n);
-// Split-K scratch (elements) for a filter GEMM of n columns: the largest
-// piece's need, pieces running one after another.
-size_t filter_partial_elems(int64_t N, int n);
+
 void filter_gemm(const Z *H, int64_t ldh, int64_t N, const Z *Y, int64_t ldy,
                  const Z *X, int64_t ldx, Z *W, int64_t ldw, int n, double a,
                  double b, double g, Z *part, hipStream_t s,
@@ -110,9 +73,6 @@ void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s);
 
 // FP32 filter GEMM on the complex64 shadow Hc (mixed precision), same
 // contract as filter_gemm; partials: filter32_partial_elems(N, n) complex64.
-FilterPlan filter32_plan(int64_t N, int n);
-std::vector<FilterPiece> filter32_pieces(int64_t N, int n);
-size_t filter32_partial_elems(int64_t N, int n);
 void filter32_gemm(const C *H, int64_t ldh, int64_t N, const C *Y, int64_t ldy,
                    const C *X, int64_t ldx, C *W, int64_t ldw, int n, float a,
                    float b, float g, C *part, hipStream_t s,
@@ -187,16 +147,15 @@ void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
 // Reduced Hermitian eigenproblem by cyclic Jacobi.  A: n x n row-major
 // (overwritten).  On return w (device, ascending) and Y (row-major, columns
 // are eigenvectors).  work: jacobi_work_elems(n) complex elements.
-// Jacobi sweeps captured as HIP graphs (one per order n and buffer set,
-// one for each ping-pong parity) and replayed once per sweep; owned by one
-// solve, which passes it to every jacobi_eig call.
+// Jacobi sweeps as HIP graphs (one per order n and buffer set, one for
+// each ping-pong parity, built node by node) replayed once per sweep;
+// owned by one solve, which passes it to every jacobi_eig call.
 struct JacobiGraphs {
     struct Entry {
         int n;
         const void *A, *work;
         hipGraphExec_t exec[2];
     };
-    hipStream_t cap = nullptr;   // capture stream (never runs work)
     hipStream_t used = nullptr;  // stream the graphs were launched on
     std::vector<Entry> entries;
     JacobiGraphs() = default;

@@ -350,7 +350,6 @@ JacobiGraphs::~JacobiGraphs() {
     for (auto &e : entries)
         for (auto x : e.exec)
             if (x) (void)hipGraphExecDestroy(x);
-    if (cap) (void)hipStreamDestroy(cap);
 }
 
 namespace {
@@ -369,29 +368,57 @@ void launch_sweep(Z *A, Z *A2, Z *V, Z *V2, int n, int m, int grid, double *dnor
     check_launch("k_offnorm");
 }
 
-// The two captured sweeps for this order and these buffers (parity 0 starts
-// from (A, V), parity 1 from (A2, V2)); captured on first use.
+// Appends one kernel node after `dep` (none if null); returns the node.
+template <typename... Args>
+hipGraphNode_t add_kernel(hipGraph_t g, hipGraphNode_t dep, void (*fn)(Args...), dim3 grid,
+                          dim3 block, Args... args) {
+    void *argp[] = {static_cast<void *>(&args)...};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void *>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = argp;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    CHASE_HIP(hipGraphAddKernelNode(&node, g, dep ? &dep : nullptr, dep ? 1 : 0, &kp));
+    return node;
+}
+
+// The two sweep graphs for this order and these buffers (parity 0 starts
+// from (A, V), parity 1 from (A2, V2)), built node by node on first use:
+// a chain of the m - 1 round kernels and the off-norm kernel.  Building the
+// graph explicitly (no stream capture) leaves every stream of the process
+// free to work meanwhile.
 const hipGraphExec_t *sweep_graphs(JacobiGraphs &g, Z *A, Z *A2, Z *V, Z *V2, int n, int m,
                                    int grid, double *dnorm, Z *work) {
     for (auto &e : g.entries)
         if (e.n == n && e.A == A && e.work == work) return e.exec;
-    if (!g.cap) CHASE_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
     JacobiGraphs::Entry e{n, A, work, {nullptr, nullptr}};
     for (int par = 0; par < 2; ++par) {
         hipGraph_t gr = nullptr;
-        CHASE_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+        CHASE_HIP(hipGraphCreate(&gr, 0));
+        hipError_t ie = hipSuccess;
         try {
-            if (par == 0) launch_sweep(A, A2, V, V2, n, m, grid, dnorm, g.cap);
-            else launch_sweep(A2, A, V2, V, n, m, grid, dnorm, g.cap);
+            Z *a = par ? A2 : A, *a2 = par ? A : A2;
+            Z *v = par ? V2 : V, *v2 = par ? V : V2;
+            hipGraphNode_t last = nullptr;
+            for (int r = 0; r < m - 1; ++r) {
+                last = add_kernel(gr, last, k_jacobi_round, dim3(grid), dim3(256),
+                                  static_cast<const Z *>(a), a2, static_cast<const Z *>(v),
+                                  v2, n, m, r);
+                std::swap(a, a2);
+                std::swap(v, v2);
+            }
+            add_kernel(gr, last, k_offnorm, dim3(1), dim3(1024), static_cast<const Z *>(a), n,
+                       dnorm);
+            ie = hipGraphInstantiate(&e.exec[par], gr, nullptr, nullptr, 0);
         } catch (...) {
-            (void)hipStreamEndCapture(g.cap, &gr);
-            if (gr) (void)hipGraphDestroy(gr);
+            (void)hipGraphDestroy(gr);
             for (auto x : e.exec)
                 if (x) (void)hipGraphExecDestroy(x);
             throw;
         }
-        CHASE_HIP(hipStreamEndCapture(g.cap, &gr));
-        const hipError_t ie = hipGraphInstantiate(&e.exec[par], gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (ie != hipSuccess) {
             for (auto x : e.exec)

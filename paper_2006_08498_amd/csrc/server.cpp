@@ -301,11 +301,8 @@ void run_one(chase_server *s, Request *r, int slot) {
             }
             H = reinterpret_cast<const Z *>(dH);
         }
-        // No graph capture in worker threads: a capture in progress would make
-        // the callers' legacy-default-stream work fail meanwhile.
-        chase_opts ro = r->opts;
-        ro.graphs = 0;
-        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, ro, s->broker.get()};
+        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts,
+                  s->broker.get()};
         Result R = solve(p, dW, reinterpret_cast<Z *>(dV), r->N, st);
         r->eigvals = std::move(R.eigvals);
         r->resid = std::move(R.resid);

@@ -38,8 +38,8 @@ CSRC = os.path.join(HERE, "csrc")
 
 # Sources that define each filter kernel and its launch plan.
 KERNEL_SOURCES = {
-    "k_filter": ("k_filter_kern.h", "k_filter.hip", "k_filter_wide.hip", "common.h"),
-    "k_filter32": ("k_filter32.hip", "common.h"),
+    "k_filter": ("k_filter_kern.h", "k_filter.hip", "k_filter_wide.hip", "k_filter_plan.h"),
+    "k_filter32": ("k_filter32.hip", "k_filter_plan.h"),
 }
 
 

@@ -50,7 +50,7 @@ def test_defaults():
     o = chase.default_opts()
     assert (o.precision, o.max_iter, o.initial_degree, o.degree_extra,
             o.lanczos_steps, o.lanczos_runs, o.seed) == (0, 100, 20, 2, 25, 4, 0)
-    assert o.switch_tol == 1e-7 and o.dV0 is None and o.profile == 0 and o.graphs == 0
+    assert o.switch_tol == 1e-7 and o.dV0 is None and o.profile == 0 and o.graphs == 1
 
 
 @pytest.mark.parametrize("args,msg", [
