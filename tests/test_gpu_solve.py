@@ -238,3 +238,45 @@ def test_largest_subspace_1024():
     r = chase.solve(dev_colmajor(H), nev, nex, 1e-10, 20)
     assert r.status == chase.CHASE_OK
     _check_against_oracle(H, r, nev)
+
+
+def test_degenerate_eigenvalue_across_the_cut():
+    """lambda_nev = lambda_{nev+1} exactly (a triple eigenvalue straddling
+    the cut) and a 5-fold one inside the wanted set: any orthonormal basis
+    of a degenerate eigenspace is correct, so eigenvalues, residuals and
+    orthogonality are checked, and the returned vectors of each degenerate
+    eigenvalue must lie in its planted eigenspace."""
+    torch_cuda()
+    N, nev, nex = 800, 12, 8
+    rng = np.random.default_rng(3)
+    lam = np.sort(np.concatenate([[1.0, 1.1], [1.3] * 5, [1.5, 1.6, 1.7, 1.8],
+                                  [2.0] * 3, rng.uniform(2.5, 9.0, N - 14)]))
+    H, lam, Q = synth.planted_matrix(N, seed=5, lam=lam)
+    r = chase.solve(dev_colmajor(H), nev, nex, 1e-10, 20)
+    assert r.status == chase.CHASE_OK
+    assert np.abs(r.eigvals - lam[:nev]).max() <= 1e-10 * lam.max()
+    V = host(r.V)
+    res = np.linalg.norm(H @ V - V * r.eigvals[None, :], axis=0) / lam.max()
+    assert res.max() <= 1e-10
+    assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-12
+    for value in (1.3, 2.0):
+        cols = np.nonzero(np.abs(r.eigvals - value) < 1e-6)[0]
+        P = Q[:, np.abs(lam - value) < 1e-12]
+        # residual / gap bounds the part outside the planted eigenspace
+        out = np.linalg.norm(V[:, cols] - P @ (P.conj().T @ V[:, cols]), axis=0)
+        assert out.max() <= 1e-8, out.max()
+
+
+def test_scalar_matrix():
+    """H = c I: every vector is an eigenvector, Lanczos breaks down at once
+    and the filter interval is empty; the solve must return c with
+    orthonormal vectors."""
+    torch = torch_cuda()
+    N, nev, nex = 300, 6, 4
+    H = 3.25 * np.eye(N, dtype=np.complex128)
+    r = chase.solve(dev_colmajor(H), nev, nex, 1e-10, 20)
+    assert r.status == chase.CHASE_OK
+    assert np.all(np.abs(r.eigvals - 3.25) <= 1e-12)
+    V = host(r.V)
+    assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-12
+    assert np.linalg.norm(H @ V - V * r.eigvals[None, :], axis=0).max() <= 1e-10 * 3.25
