@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 MFMA (published)
+# The headline metric: time to the lowest nev eigenpairs at residual 1e-10
+# (`value`), with the filter's TFLOP/s and, for serving, p50/p99 latency
+# reported beside it on the same line.
+METRIC = "time-to-nev eigenpairs @res 1e-10; filter TFLOP/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -126,7 +130,8 @@ def run_serve(args):
         worst = max(worst, rel)
         del H
     out = {
-        "metric": "p50/p99 solve latency",
+        "metric": METRIC,
+        "value_is": "p50 solve latency (s)",
         "value": p50,
         "unit": "s",
         "n_gpus": 1,
@@ -449,7 +454,8 @@ def main():
                                "copy-calibrated)"
 
     out = {
-        "metric": "time-to-nev eigenpairs @res 1e-10",
+        "metric": METRIC,
+        "value_is": "time to the lowest nev eigenpairs at residual 1e-10 (s per solve)",
         "value": per,
         "unit": "s",
         "n_gpus": 1,
