@@ -320,21 +320,24 @@ int chase_lanczos(const chase_z *dH, int64_t N, int64_t ldh,
         hipStream_t s = S(stream);
         const size_t vb = (size_t)N * r * sizeof(Z);
         const size_t fp = filter_partial_elems(N, r) * sizeof(Z);
-        DevBuf buf(3 * vb + fp + 2 * (size_t)k * r * sizeof(double) + 1024, s);
+        const size_t ls = lanczos_scratch_elems(N, r) * sizeof(double);
+        DevBuf buf(3 * vb + fp + 2 * (size_t)k * r * sizeof(double) + ls + 1024, s);
         char *b = buf.as<char>();
         Z *v = reinterpret_cast<Z *>(b);
         Z *vp = reinterpret_cast<Z *>(b + vb);
         Z *w = reinterpret_cast<Z *>(b + 2 * vb);
         double *al = reinterpret_cast<double *>(b + 3 * vb);
         double *be = al + (size_t)k * r;
+        double *lsc = be + (size_t)k * r;
         Z *part = reinterpret_cast<Z *>(
-            (reinterpret_cast<uintptr_t>(be + (size_t)k * r) + 255) & ~uintptr_t(255));
+            (reinterpret_cast<uintptr_t>(lsc + lanczos_scratch_elems(N, r)) + 255) &
+            ~uintptr_t(255));
         copy_block(reinterpret_cast<const Z *>(dV0), ldv0, w, r, N, r, s);
-        lanczos_update(v, vp, w, r, N, r, al, be, 0, 1, s);
+        lanczos_update(v, vp, w, r, N, r, al, be, 0, 1, lsc, s);
         for (int j = 0; j < k; ++j) {
             filter_gemm(reinterpret_cast<const Z *>(dH), ldh, N, v, r, nullptr, r,
                         w, r, r, 1.0, 0.0, 0.0, part, s);
-            lanczos_update(v, vp, w, r, N, r, al, be, j, 0, s);
+            lanczos_update(v, vp, w, r, N, r, al, be, j, 0, lsc, s);
         }
         CHASE_HIP(hipMemcpyAsync(h_alpha, al, sizeof(double) * k * r,
                                  hipMemcpyDeviceToHost, s));

@@ -133,9 +133,10 @@ void check_finite(const Z *H, int64_t ldh, int64_t N, int *flag, hipStream_t s);
 // row-major N x r blocks):  alpha = Re v^H w;  w -= alpha v + beta_prev vp;
 // beta = ||w||;  vp <- v;  v <- w / beta.  Writes alpha/beta for `step`.
 // If `normalise_only`, just sets v <- v0 / ||v0|| and vp <- 0.
+size_t lanczos_scratch_elems(int64_t N, int r);
 void lanczos_update(Z *v, Z *vp, Z *w, int64_t ld, int64_t N, int r,
                     double *alpha, double *beta, int step, int normalise_only,
-                    hipStream_t s);
+                    double *scratch, hipStream_t s);
 
 // ------------------------------------------------- small dense (n <= 512)
 // G (n x n Hermitian, row-major ld n) -> in place lower Cholesky factor of

@@ -225,13 +225,19 @@ __global__ __launch_bounds__(256) void k_colnorm_part(
     }
 }
 
-__global__ void k_colnorm_final(const double *__restrict__ part, int nblk,
-                                int n, double *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// One wave per column: lanes take strided partials, then a butterfly sum
+// (a fixed order, so the result is deterministic).
+__global__ __launch_bounds__(256) void k_colnorm_final(const double *__restrict__ part,
+                                                       int nblk, int n,
+                                                       double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;   // uniform per wave
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * n + j];
-    out[j] = sqrt(acc);
+    for (int b = lane; b < nblk; b += 64) acc += part[(int64_t)b * n + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) out[j] = sqrt(acc);
 }
 
 int norm_blocks(int64_t N) {
@@ -419,57 +425,88 @@ __device__ double block_sum(double v, double *sh) {
     return out;
 }
 
-__global__ __launch_bounds__(1024) void k_lanczos(Z *v, Z *vp, Z *w,
-                                                  int64_t ld, int N, int r,
-                                                  double *alpha, double *beta,
-                                                  int step, int normalise_only) {
-    __shared__ double sh[1024];
-    const int run = blockIdx.x;
-    const int t = threadIdx.x;
-    if (normalise_only) {
-        double s = 0.0;
-        for (int i = t; i < N; i += 1024) {
-            const Z x = w[(int64_t)i * ld + run];
-            s += x.x * x.x + x.y * x.y;
-        }
-        const double nrm = sqrt(block_sum<1024>(s, sh));
-        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int i = t; i < N; i += 1024) {
-            const Z x = w[(int64_t)i * ld + run];
-            v[(int64_t)i * ld + run] = Z{x.x * inv, x.y * inv};
-            vp[(int64_t)i * ld + run] = Z{0.0, 0.0};
-        }
-        return;
-    }
+// Lanczos vector update for r independent runs (columns of N x r
+// row-major blocks v, vp, w), in three launches over a grid of blocks x
+// runs; partial sums go to `part` (2 * blocks * r doubles) and every block
+// reduces them in the same fixed order:
+//   dot:    part[run][b] = Re(v^H w) over the block's rows;
+//   update: alpha = sum; w -= alpha v + beta_prev vp; part2 = |w|^2 partial;
+//   scale:  beta = sqrt(sum); vp = v; v = w / beta.
+// The first step (normalise_only) skips dot and update: v = w / |w|, vp = 0.
+constexpr int kLzThreads = 256;
+
+__device__ double lz_sum_parts(const double *p, int nb, double *sh) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kLzThreads) acc += p[b];
+    return block_sum<kLzThreads>(acc, sh);
+}
+
+__global__ __launch_bounds__(kLzThreads) void k_lz_dot(const Z *v, const Z *w, int64_t ld,
+                                                       int N, int rows, double *part) {
+    __shared__ double sh[kLzThreads];
+    const int b = blockIdx.x, run = blockIdx.y, nb = gridDim.x;
+    const int i1 = min(N, (b + 1) * rows);
     double s = 0.0;
-    for (int i = t; i < N; i += 1024) {
-        const Z a = v[(int64_t)i * ld + run], b = w[(int64_t)i * ld + run];
-        s += a.x * b.x + a.y * b.y;     // Re(conj(v) w)
+    for (int i = b * rows + threadIdx.x; i < i1; i += kLzThreads) {
+        const Z a = v[(int64_t)i * ld + run], c = w[(int64_t)i * ld + run];
+        s += a.x * c.x + a.y * c.y;     // Re(conj(v) w)
     }
-    const double al = block_sum<1024>(s, sh);
-    const double bp = step > 0 ? beta[(step - 1) * r + run] : 0.0;
-    s = 0.0;
-    for (int i = t; i < N; i += 1024) {
+    s = block_sum<kLzThreads>(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)run * nb + b] = s;
+}
+
+__global__ __launch_bounds__(kLzThreads) void k_lz_update(const Z *v, const Z *vp, Z *w,
+                                                          int64_t ld, int N, int rows,
+                                                          const double *part, double *part2,
+                                                          const double *beta_prev,
+                                                          int normalise_only) {
+    __shared__ double sh[kLzThreads];
+    const int b = blockIdx.x, run = blockIdx.y, nb = gridDim.x;
+    const double al = normalise_only ? 0.0 : lz_sum_parts(part + (int64_t)run * nb, nb, sh);
+    const double bp = (normalise_only || !beta_prev) ? 0.0 : beta_prev[run];
+    const int i1 = min(N, (b + 1) * rows);
+    double s = 0.0;
+    for (int i = b * rows + threadIdx.x; i < i1; i += kLzThreads) {
         const int64_t o = (int64_t)i * ld + run;
-        const Z a = v[o], c = vp[o];
-        Z b = w[o];
-        b.x -= al * a.x + bp * c.x;
-        b.y -= al * a.y + bp * c.y;
-        w[o] = b;
-        s += b.x * b.x + b.y * b.y;
+        Z c = w[o];
+        if (!normalise_only) {
+            const Z a = v[o], d = vp[o];
+            c.x -= al * a.x + bp * d.x;
+            c.y -= al * a.y + bp * d.y;
+            w[o] = c;
+        }
+        s += c.x * c.x + c.y * c.y;
     }
-    const double be = sqrt(block_sum<1024>(s, sh));
+    s = block_sum<kLzThreads>(s, sh);
+    if (threadIdx.x == 0) part2[(int64_t)run * nb + b] = s;
+}
+
+__global__ __launch_bounds__(kLzThreads) void k_lz_scale(Z *v, Z *vp, const Z *w, int64_t ld,
+                                                         int N, int rows, const double *part,
+                                                         const double *part2, double *alpha,
+                                                         double *beta, int normalise_only) {
+    __shared__ double sh[kLzThreads];
+    const int b = blockIdx.x, run = blockIdx.y, nb = gridDim.x;
+    const double be = sqrt(lz_sum_parts(part2 + (int64_t)run * nb, nb, sh));
     const double inv = be > 0.0 ? 1.0 / be : 0.0;
-    for (int i = t; i < N; i += 1024) {
+    const int i1 = min(N, (b + 1) * rows);
+    for (int i = b * rows + threadIdx.x; i < i1; i += kLzThreads) {
         const int64_t o = (int64_t)i * ld + run;
-        const Z a = v[o], b = w[o];
-        vp[o] = a;
-        v[o] = Z{b.x * inv, b.y * inv};
+        const Z c = w[o];
+        vp[o] = normalise_only ? Z{0.0, 0.0} : v[o];
+        v[o] = Z{c.x * inv, c.y * inv};
     }
-    if (t == 0) {
-        alpha[step * r + run] = al;
-        beta[step * r + run] = be;
+    if (!normalise_only && b == 0) {
+        const double al = lz_sum_parts(part + (int64_t)run * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            alpha[run] = al;
+            beta[run] = be;
+        }
     }
+}
+
+int lz_blocks(int64_t N) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(128, (N + 1023) / 1024));
 }
 
 inline int grid_for(int64_t total) {
@@ -536,7 +573,7 @@ void col_norms(const Z *V, int64_t ldv, const Z *V2, int64_t ldv2,
     hipLaunchKernelGGL(k_colnorm_part, dim3(nblk), dim3(256), 0, s, V, ldv, V2,
                        ldv2, theta, (int)N, n, rows, part);
     check_launch("k_colnorm_part");
-    hipLaunchKernelGGL(k_colnorm_final, dim3((n + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_colnorm_final, dim3((n + 3) / 4), dim3(256), 0, s,
                        part, nblk, n, out);
     check_launch("k_colnorm_final");
 }
@@ -615,12 +652,27 @@ void check_finite(const Z *H, int64_t ldh, int64_t N, int *flag,
     check_launch("k_check_finite");
 }
 
+size_t lanczos_scratch_elems(int64_t N, int r) { return (size_t)2 * lz_blocks(N) * r; }
+
 void lanczos_update(Z *v, Z *vp, Z *w, int64_t ld, int64_t N, int r,
                     double *alpha, double *beta, int step, int normalise_only,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_lanczos, dim3(r), dim3(1024), 0, s, v, vp, w, ld,
-                       (int)N, r, alpha, beta, step, normalise_only);
-    check_launch("k_lanczos");
+                    double *scratch, hipStream_t s) {
+    const int nb = lz_blocks(N);
+    const int rows = (int)((N + nb - 1) / nb);
+    double *part = scratch, *part2 = scratch + (size_t)nb * r;
+    const dim3 grid(nb, r);
+    if (!normalise_only) {
+        hipLaunchKernelGGL(k_lz_dot, grid, dim3(kLzThreads), 0, s, v, w, ld, (int)N, rows, part);
+        check_launch("k_lz_dot");
+    }
+    const double *bprev = step > 0 ? beta + (size_t)(step - 1) * r : nullptr;
+    hipLaunchKernelGGL(k_lz_update, grid, dim3(kLzThreads), 0, s, v, vp, w, ld, (int)N, rows,
+                       part, part2, bprev, normalise_only);
+    check_launch("k_lz_update");
+    hipLaunchKernelGGL(k_lz_scale, grid, dim3(kLzThreads), 0, s, v, vp, w, ld, (int)N, rows,
+                       part, part2, alpha + (size_t)step * r, beta + (size_t)step * r,
+                       normalise_only);
+    check_launch("k_lz_scale");
 }
 
 }  // namespace chase

@@ -71,6 +71,7 @@ Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o) {
     L.Lw = take((size_t)N * L.r * zb);
     L.Lal = take((size_t)L.k * L.r * sizeof(double));
     L.Lbe = take((size_t)L.k * L.r * sizeof(double));
+    L.Lpart = take(lanczos_scratch_elems(N, L.r) * sizeof(double));
     L.mixed = o.precision == CHASE_MIXED;
     L.Hc = L.Vc = L.Bc = L.fpart32 = 0;
     if (L.mixed) {
@@ -343,6 +344,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     Z *Lw = reinterpret_cast<Z *>(base + Lo.Lw);
     double *Lal = reinterpret_cast<double *>(base + Lo.Lal);
     double *Lbe = reinterpret_cast<double *>(base + Lo.Lbe);
+    double *Lpart = reinterpret_cast<double *>(base + Lo.Lpart);
     C *Hc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Hc) : nullptr;
     C *Vc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Vc) : nullptr;
     C *Bc = Lo.mixed ? reinterpret_cast<C *>(base + Lo.Bc) : nullptr;
@@ -424,10 +426,10 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     hipEvent_t l0 = E.make(), l1 = E.make();
     CHASE_HIP(hipEventRecord(l0, s));
     random_block(Lw, r, N, r, o.seed, 1u, s);
-    lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, 0, 1, s);
+    lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, 0, 1, Lpart, s);
     for (int j = 0; j < k; ++j) {
         gemm_other(Lv, r, Lw, r, r);
-        lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, j, 0, s);
+        lanczos_update(Lv, Lvp, Lw, r, N, r, Lal, Lbe, j, 0, Lpart, s);
     }
     CHASE_HIP(hipEventRecord(l1, s));
     CHASE_HIP(hipMemcpyAsync(h_al, Lal, sizeof(double) * k * r, hipMemcpyDeviceToHost, s));

@@ -13,7 +13,7 @@ struct Layout {
     int64_t N;
     int ne, r, k;
     size_t V, B1, W, T, fpart, gpart, G, Bq, cwork, Y, jwork, theta, resid,
-        npart, perm, info, Lv, Lvp, Lw, Lal, Lbe;
+        npart, perm, info, Lv, Lvp, Lw, Lal, Lbe, Lpart;
     // CHASE_MIXED only (size 0 otherwise): complex64 shadow of H, two FP32
     // vector blocks and the FP32 split-K partials.
     size_t Hc, Vc, Bc, fpart32;

@@ -4,6 +4,8 @@
     python -m paper_2006_08498_amd.profsum traffic --fetch D --write D \
         --copy-fetch D --copy-write D --copy-bytes B [--match SUBSTR] [--workload W]
     python -m paper_2006_08498_amd.profsum counters DIR [--match SUBSTR]
+    python -m paper_2006_08498_amd.profsum bandwidth --trace D --fetch D --write D \
+        --copy-fetch D --copy-write D --copy-bytes B [--match A,B,...]
 
 `stats` prints the rows of the kernel-statistics CSV under DIR (from
 `rocprofv3 --kernel-trace --stats --output-format csv`) whose kernel name
@@ -12,6 +14,10 @@ contains SUBSTR, plus their call-weighted average duration.
 `counters` prints, per kernel, the mean per dispatch of every counter of
 a `--pmc` run (for instance MfmaUtil, the percentage of cycles the MFMA
 units were busy).
+
+`bandwidth` joins a kernel trace with the two counter runs: per kernel,
+the average duration and the calibrated HBM bytes per dispatch, hence the
+achieved bandwidth against the HBM peak (8 TB/s).
 
 `traffic` turns two counter runs (`--pmc FETCH_SIZE`, then `--pmc
 WRITE_SIZE`, KiB per dispatch) into HBM bytes per launch.  Each counter is
@@ -154,6 +160,47 @@ def cmd_counters(a):
         print(f"| {k} | {nd} | " + " | ".join(cells) + " |")
 
 
+def _calibration(a):
+    cf = counter_values(a.copy_fetch, "copy", "FETCH_SIZE")
+    cw = counter_values(a.copy_write, "copy", "WRITE_SIZE")
+    cf_mean = sum(sum(v) for v in cf.values()) / max(1, sum(len(v) for v in cf.values()))
+    cw_mean = sum(sum(v) for v in cw.values()) / max(1, sum(len(v) for v in cw.values()))
+    if cf_mean <= 0 or cw_mean <= 0:
+        sys.exit("copy-kernel counters missing")
+    return a.copy_bytes / (cf_mean * 1024.0), a.copy_bytes / (cw_mean * 1024.0)
+
+
+def cmd_bandwidth(a):
+    """Per kernel: trace duration and copy-calibrated HBM bytes per dispatch,
+    hence the achieved HBM bandwidth against the peak."""
+    kf, kw = _calibration(a)
+    dur = {}
+    for name, calls, avg, _tot in kernel_stats(a.trace, ""):
+        dur[_short(name)] = (calls, avg)
+    fv = counter_values(a.fetch, "", "FETCH_SIZE")
+    wv = counter_values(a.write, "", "WRITE_SIZE")
+    rows = []
+    for name in fv:
+        k = _short(name)
+        if a.match and not any(m in k for m in a.match.split(",")):
+            continue
+        if k not in dur or name not in wv:
+            continue
+        rd = kf * 1024.0 * sum(fv[name]) / len(fv[name])
+        wr = kw * 1024.0 * sum(wv[name]) / len(wv[name])
+        calls, avg = dur[k]
+        gbs = (rd + wr) / (avg * 1e-9) / 1e9
+        rows.append((calls * avg, k, calls, avg, rd, wr, gbs))
+    print(f"HBM peak {a.peak_gbs:.0f} GB/s; bytes per dispatch from FETCH_SIZE x {kf:.4f} "
+          f"and WRITE_SIZE x {kw:.4f} KiB")
+    print()
+    print("| kernel | calls (trace) | avg us | read MB | written MB | GB/s | of peak |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for _t, k, calls, avg, rd, wr, gbs in sorted(rows, reverse=True):
+        print(f"| {k} | {calls} | {avg / 1e3:.1f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | "
+              f"{gbs:.0f} | {gbs / a.peak_gbs:.2f} |")
+
+
 def read_record(path):
     """The traffic record of a committed profile summary, or None."""
     try:
@@ -178,11 +225,19 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--match", default="k_filter<")
     t.add_argument("--workload", default="planted24k")
+    bw = sub.add_parser("bandwidth")
+    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+        bw.add_argument("--" + k.replace("_", "-"), required=True)
+    bw.add_argument("--copy-bytes", type=float, required=True)
+    bw.add_argument("--match", default="",
+                    help="comma-separated substrings of the kernels to list (all if empty)")
+    bw.add_argument("--peak-gbs", type=float, default=8000.0)
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--match", default="k_filter<")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters,
+     "bandwidth": cmd_bandwidth}[a.cmd](a)
 
 
 if __name__ == "__main__":
