@@ -46,6 +46,13 @@ WORKLOADS = {
 }
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA (published)
 
+# Sequence of nearby eigenproblems: H_t = H_0 + t * delta * P, t = 0 .. T-1
+# (T = --steps), H_0 the D + K matrix of the seed (std 0.02, decay 200) and
+# P another D + K draw (seed + 100).  Each H_t is solved cold and warm-started
+# from the previous solve's whole search block (shortened Lanczos).
+SEQ = dict(kind="dk", N=24000, nev=100, nex=40, degree_max=20, tol=1e-10, std=0.02,
+           decay=200.0, precision="fp64", delta=1e-5)
+
 # Serving: 128 requests, Poisson arrivals at 4 per second (seed 42), N uniform
 # in {4000, ..., 20000}, nev uniform in [30, 150], nex = round-half-up(0.4
 # nev), D + K (std 0.02, decay 200) with seed 1000 + r, generated on the
@@ -279,116 +286,11 @@ def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs
     return infos, (time.perf_counter() - t0) / steps, r
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="planted24k",
-                    choices=sorted(WORKLOADS) + ["serve128"])
-    ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
-    ap.add_argument("--fuse", type=int, default=0,
-                    help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
-    ap.add_argument("--policy", choices=("fifo", "sjf"), default="fifo",
-                    help="serve128: admission in arrival order or shortest estimated work "
-                         "first (with aging)")
-    ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64",
-                    help="serve128: precision of the served solves")
-    ap.add_argument("--serve-solo-baseline", action="store_true",
-                    help="serve128: also time every request alone, one after another")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--seeds", type=lambda t: [int(x) for x in t.split(",") if x != ""],
-                    default=None,
-                    help="comma-separated generator seeds (e.g. 0,1,2,3,4): time each, "
-                         "report each and their median as value")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--h-cache", default="",
-                    help="file holding the generated matrix: written if absent, "
-                         "read if present (keeps matrix generation out of profiled runs)")
-    ap.add_argument("--switch-tol", type=float, default=None,
-                    help="mixed workloads: residual / ||H|| above which a vector is "
-                         "filtered in FP32 (library default if omitted)")
-    ap.add_argument("--graphs", type=int, choices=(0, 1), default=None,
-                    help="Jacobi sweeps as HIP graph replays (1) or direct launches (0); "
-                         "library default if omitted")
-    ap.add_argument("--no-fp64-reference", action="store_true",
-                    help="mixed workloads: skip timing the plain FP64 solve")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="only run a plain device copy of this many MiB (5 times): "
-                         "the reference kernel for scaling HBM byte counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                                   "use --gpus 1 (multi-GPU sharding is a design note)"}))
-        sys.exit(2)
-
-    import torch
-    from paper_2006_08498_amd import chase
-
-    if args.copy_probe_mib:
-        from paper_2006_08498_amd import synth
-        nbytes = args.copy_probe_mib << 20
-        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            synth.device_copy(a, b)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
-        return
-    if args.workload == "serve128":
-        run_serve(args)
-        return
-
-    w = WORKLOADS[args.workload]
-    N, nev, nex = w["N"], w["nev"], w["nex"]
-    t0 = time.perf_counter()
-    if args.h_cache and os.path.exists(args.h_cache):
-        # A matrix generated earlier by this script (raw complex128, the
-        # device tensor's memory order) and its planted eigenvalues.
-        log(f"workload {args.workload}: loading N={N} from {args.h_cache}")
-        Hh = np.fromfile(args.h_cache, dtype=np.complex128).reshape(N, N)
-        H = torch.from_numpy(Hh).cuda()
-        del Hh
-        lam = np.load(args.h_cache + ".lam.npy") if w["kind"] == "planted" else None
-        if w["kind"] != "planted":
-            H = H.t()   # the D + K generator writes column-major memory
-    else:
-        log(f"workload {args.workload}: generating N={N} on the device")
-        H, lam = make_matrix(w, args.seed)
-        if args.h_cache:
-            mem = H if H.stride(1) == 1 else H.t()
-            mem.cpu().numpy().tofile(args.h_cache)
-            if lam is not None:
-                np.save(args.h_cache + ".lam.npy", lam)
-    torch.cuda.synchronize()
-    log(f"generated in {time.perf_counter() - t0:.1f} s")
-    precision = chase.CHASE_MIXED if w["precision"] == "mixed" else chase.CHASE_FP64
-    o = chase.default_opts(precision=precision)
-    ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8, device="cuda")
-    infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed,
-                               args.switch_tol, args.graphs)
-    chk = check_result(H, r, lam, w["tol"])
-    log(f"check: {chk}")
-    per_seed = None
-    if args.seeds:
-        # The same workload over several generator seeds: each seed's time
-        # per solve and checks; `value` becomes their median.
-        per_seed = [{"seed": args.seed, "value": per, "iterations": r.info["iterations"],
-                     "check": chk}]
-        for sd in args.seeds:
-            if sd == args.seed:
-                continue
-            del H
-            H, lam_s = make_matrix(w, sd)
-            torch.cuda.synchronize()
-            inf_s, per_s, r_s = run_solves(H, w, ws, precision, args.steps, args.warmup, sd,
-                                           args.switch_tol, args.graphs)
-            per_seed.append({"seed": sd, "value": per_s, "iterations": r_s.info["iterations"],
-                             "check": check_result(H, r_s, lam_s, w["tol"])})
-            log(f"seed {sd}: {per_s:.4f} s per solve")
-        per = float(np.median([e["value"] for e in per_seed]))
-
+def kernel_roofline(infos, N, workload):
+    """Totals of the timed solves' info records, the dominant kernel's
+    roofline (with the committed traffic record while its sources match),
+    each phase's fraction of its roofline, mean phase times and the FP64 /
+    FP32 filter kernel rates."""
     def sums(infos):
         keys = ("filter_flops", "t_filter_kernels", "filter_launches", "t_filter",
                 "matvecs_filter", "matvecs_filter_fp32", "t_filter32_kernels",
@@ -446,12 +348,222 @@ def main():
             "frac": max(t_mfma, t_hbm) / t if t > 0 else 0.0}
 
     from paper_2006_08498_amd import profsum
-    rec = profsum.read_record(os.path.join(ROOT, "profiles", f"{kern}_{args.workload}.md"))
+    rec = profsum.read_record(os.path.join(ROOT, "profiles", f"{kern}_{workload}.md"))
     if rec and rec.get("sources_digest") == profsum.sources_digest(kern) \
-            and rec.get("workload") == args.workload:
+            and rec.get("workload") == workload:
         roof["traffic"] = rec["bytes_per_launch"]
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, " \
                                "copy-calibrated)"
+    return S, roof, phase_roof, phases, ach64, ach32
+
+
+def run_sequence(args):
+    """Warm-started chain against cold solves of the same matrices."""
+    import torch
+    from paper_2006_08498_amd import chase, synth
+    w = SEQ
+    N, nev, nex, tol, dmax = w["N"], w["nev"], w["nex"], w["tol"], w["degree_max"]
+    ne, T = nev + nex, args.steps
+    log(f"workload seq24k: generating H_0 and P (N={N}) on the device")
+    H0 = synth.dk_matrix_device(N, seed=args.seed, std=w["std"], decay=w["decay"])
+    P = synth.dk_matrix_device(N, seed=args.seed + 100, std=w["std"], decay=w["decay"])
+    H = H0.clone()
+
+    def form(t):
+        # Elementwise, so H_t stays Hermitian to the last bit.
+        H.copy_(H0)
+        H.add_(P, alpha=t * w["delta"])
+        torch.cuda.synchronize()
+
+    ws = torch.empty(chase.workspace_bytes(N, nev, nex, chase.default_opts()),
+                     dtype=torch.uint8, device="cuda")
+    base = dict(profile=1, seed=args.seed)
+    form(0)
+    for i in range(args.warmup):
+        r = chase.solve(H, nev, nex, tol, dmax, workspace=ws, **base)
+        log(f"warmup {i}: {r.info['t_total']:.3f} s")
+
+    def timed(**kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = chase.solve(H, nev, nex, tol, dmax, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    V = None
+    steps, warm_infos, cold_infos = [], [], []
+    t_warm = t_cold = 0.0
+    for t in range(T):
+        form(t)
+        c, tc = timed(**base)
+        kw = dict(base, out_cols=ne)
+        if V is not None:
+            kw.update(V0=V, lanczos_steps=10, lanczos_runs=1)
+        r, tw = timed(**kw)
+        V = r.V
+        t_cold += tc
+        t_warm += tw
+        warm_infos.append(r.info)
+        cold_infos.append(c.info)
+        d = float(np.max(np.abs(r.eigvals - c.eigvals)))
+        steps.append({"t": t, "warm_s": tw, "cold_s": tc,
+                      "warm_iterations": r.info["iterations"],
+                      "cold_iterations": c.info["iterations"],
+                      "warm_matvecs": r.info["matvecs_filter"],
+                      "cold_matvecs": c.info["matvecs_filter"],
+                      "max_eig_diff_warm_vs_cold": d})
+        log(f"H_{t}: warm {tw:.3f} s ({r.info['iterations']} it, "
+            f"{r.info['matvecs_filter']} mat-vecs), cold {tc:.3f} s "
+            f"({c.info['iterations']} it, {c.info['matvecs_filter']} mat-vecs), "
+            f"eigenvalues differ by {d:.1e}")
+    head = chase.SolveResult(r.eigvals, r.V[:, :nev], r.resid, r.status, r.info)
+    chk = check_result(H, head, None, tol)
+    log(f"check: {chk}")
+    S, roof, phase_roof, phases, ach64, _ = kernel_roofline(warm_infos, N, "seq24k")
+    per = t_warm / T
+    out = {
+        "metric": METRIC,
+        "value_is": "time to the lowest nev eigenpairs at residual 1e-10 (s per solve), "
+                    "mean over a warm-started sequence of matrices",
+        "value": per, "unit": "s", "n_gpus": 1, "steps": T, "warmup": args.warmup,
+        "ms_per_step": per * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"seq24k: D+K sequence H_t = H_0 + t*{w['delta']}*P, "
+                               f"t < {T}, N={N} nev={nev} nex={nex} degree<={dmax} "
+                               f"tol={tol} precision=fp64",
+                   "N": N, "nev": nev, "nex": nex, "degree_max": dmax, "tol": tol,
+                   "delta": w["delta"], "matrices": T, "parallelism": "1 GPU"},
+        "cold_s_per_solve": t_cold / T,
+        "speedup_warm_over_cold": t_cold / t_warm,
+        "filter_kernel_tflops_fp64": ach64,
+        "matvecs_filter_warm": sum(i["matvecs_filter"] for i in warm_infos),
+        "matvecs_filter_cold": sum(i["matvecs_filter"] for i in cold_infos),
+        "per_matrix": steps,
+        "phases_s": phases,
+        "phase_roofline": phase_roof,
+        "check": chk,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w, args.seed, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="planted24k",
+                    choices=sorted(WORKLOADS) + ["serve128", "seq24k"])
+    ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
+    ap.add_argument("--fuse", type=int, default=0,
+                    help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
+    ap.add_argument("--policy", choices=("fifo", "sjf"), default="fifo",
+                    help="serve128: admission in arrival order or shortest estimated work "
+                         "first (with aging)")
+    ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64",
+                    help="serve128: precision of the served solves")
+    ap.add_argument("--serve-solo-baseline", action="store_true",
+                    help="serve128: also time every request alone, one after another")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", type=lambda t: [int(x) for x in t.split(",") if x != ""],
+                    default=None,
+                    help="comma-separated generator seeds (e.g. 0,1,2,3,4): time each, "
+                         "report each and their median as value")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--h-cache", default="",
+                    help="file holding the generated matrix: written if absent, "
+                         "read if present (keeps matrix generation out of profiled runs)")
+    ap.add_argument("--switch-tol", type=float, default=None,
+                    help="mixed workloads: residual / ||H|| above which a vector is "
+                         "filtered in FP32 (library default if omitted)")
+    ap.add_argument("--graphs", type=int, choices=(0, 1), default=None,
+                    help="Jacobi sweeps as HIP graph replays (1) or direct launches (0); "
+                         "library default if omitted")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="mixed workloads: skip timing the plain FP64 solve")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times): "
+                         "the reference kernel for scaling HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                                   "use --gpus 1 (multi-GPU sharding is a design note)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2006_08498_amd import chase
+
+    if args.copy_probe_mib:
+        from paper_2006_08498_amd import synth
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            synth.device_copy(a, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+        return
+    if args.workload == "serve128":
+        run_serve(args)
+        return
+    if args.workload == "seq24k":
+        run_sequence(args)
+        return
+
+    w = WORKLOADS[args.workload]
+    N, nev, nex = w["N"], w["nev"], w["nex"]
+    t0 = time.perf_counter()
+    if args.h_cache and os.path.exists(args.h_cache):
+        # A matrix generated earlier by this script (raw complex128, the
+        # device tensor's memory order) and its planted eigenvalues.
+        log(f"workload {args.workload}: loading N={N} from {args.h_cache}")
+        Hh = np.fromfile(args.h_cache, dtype=np.complex128).reshape(N, N)
+        H = torch.from_numpy(Hh).cuda()
+        del Hh
+        lam = np.load(args.h_cache + ".lam.npy") if w["kind"] == "planted" else None
+        if w["kind"] != "planted":
+            H = H.t()   # the D + K generator writes column-major memory
+    else:
+        log(f"workload {args.workload}: generating N={N} on the device")
+        H, lam = make_matrix(w, args.seed)
+        if args.h_cache:
+            mem = H if H.stride(1) == 1 else H.t()
+            mem.cpu().numpy().tofile(args.h_cache)
+            if lam is not None:
+                np.save(args.h_cache + ".lam.npy", lam)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    precision = chase.CHASE_MIXED if w["precision"] == "mixed" else chase.CHASE_FP64
+    o = chase.default_opts(precision=precision)
+    ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8, device="cuda")
+    infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed,
+                               args.switch_tol, args.graphs)
+    chk = check_result(H, r, lam, w["tol"])
+    log(f"check: {chk}")
+    per_seed = None
+    if args.seeds:
+        # The same workload over several generator seeds: each seed's time
+        # per solve and checks; `value` becomes their median.
+        per_seed = [{"seed": args.seed, "value": per, "iterations": r.info["iterations"],
+                     "check": chk}]
+        for sd in args.seeds:
+            if sd == args.seed:
+                continue
+            del H
+            H, lam_s = make_matrix(w, sd)
+            torch.cuda.synchronize()
+            inf_s, per_s, r_s = run_solves(H, w, ws, precision, args.steps, args.warmup, sd,
+                                           args.switch_tol, args.graphs)
+            per_seed.append({"seed": sd, "value": per_s, "iterations": r_s.info["iterations"],
+                             "check": check_result(H, r_s, lam_s, w["tol"])})
+            log(f"seed {sd}: {per_s:.4f} s per solve")
+        per = float(np.median([e["value"] for e in per_seed]))
+
+    S, roof, phase_roof, phases, ach64, ach32 = kernel_roofline(infos, N, args.workload)
 
     out = {
         "metric": METRIC,

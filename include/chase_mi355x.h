@@ -87,9 +87,17 @@ typedef struct chase_opts {
     double switch_tol;        /* CHASE_MIXED: residual / ||H|| above which a
                                  vector is filtered in FP32 (until FP32 stalls on
                                  it); default 1e-7, about the FP32 floor */
-    const chase_z *dV0;       /* optional warm start, N x (nev+nex),
+    const chase_z *dV0;       /* optional warm start: v0_cols columns,
                                  column-major, leading dimension N; NULL =
-                                 random start */
+                                 random start.  With a warm start the first
+                                 iteration is a Rayleigh-Ritz of the given
+                                 block without filtering: its residuals set
+                                 the first degrees and its largest Ritz value
+                                 the first damped interval, so Lanczos is
+                                 needed for the upper bound and ||H|| only
+                                 and may be shortened (lanczos_steps 10,
+                                 lanczos_runs 1 suffice for a sequence of
+                                 nearby matrices) */
     int32_t profile;          /* 1: time every filter launch with HIP events
                                  (fills t_filter_kernels) */
     int32_t graphs;           /* 1 (default): run each Jacobi sweep of the
@@ -106,6 +114,16 @@ typedef struct chase_opts {
      * pairs so far.  NULL = no callback. */
     chase_iter_fn on_iteration;
     void *on_iteration_user;
+    /* Sequences of eigenproblems (the solver's original use, Sec. "Solving
+     * the BSE eigenvalue problem on massively parallel architectures").
+     * v0_cols: columns of dV0 given, 1..nev+nex; 0 (default) = nev+nex; the
+     * rest of the start block is random.  out_cols: columns written to dV,
+     * nev..nev+nex; 0 (default) = nev.  Columns past nev hold the rest of
+     * the final search block (Ritz vectors by ascending Ritz value, same
+     * phase normalisation), so that dV of one solve warm-starts the next
+     * with v0_cols = out_cols = nev+nex. */
+    int32_t v0_cols;
+    int32_t out_cols;
     int32_t reserved[2];
 } chase_opts;
 
@@ -183,7 +201,8 @@ size_t chase_workspace_bytes(int64_t N, int32_t nev, int32_t nex,
 
 /*
  * Full form.  h_resid (nev doubles, may be NULL) receives the residual norms
- * ||H v_j - lambda_j v_j||_2.  dwork/work_bytes: caller-provided device
+ * ||H v_j - lambda_j v_j||_2.  dV holds nev columns, or o->out_cols when
+ * that is set (see chase_opts).  dwork/work_bytes: caller-provided device
  * workspace of at least chase_workspace_bytes() bytes, 256-byte aligned, or
  * NULL/0 to let the library allocate.  o == NULL means defaults.  info may
  * be NULL.  On CHASE_ENOCONV the outputs hold the current best Ritz pairs
@@ -332,6 +351,19 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
 int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
                   double tol_abs, double alpha, double beta,
                   int32_t degree_max, int32_t extra, int32_t *h_degrees);
+
+/*
+ * nex for a matrix of a series by linear interpolation in the energy cutoff
+ * (supplement Eq. S2, Sec. "Optimization of the nex value"): nex_low at
+ * e_low, nex_high at e_high, rounded to the nearest integer (halves away
+ * from zero); e outside [e_low, e_high] extrapolates, and the result is at
+ * least 0.  Host only.  Returns -1 (with chase_last_error set) unless
+ * e_high > e_low, both finite, e finite and nex_low, nex_high >= 0.  The
+ * supplement's Table S10 is reproduced with e_high = 14.32 eV, not the
+ * printed 12.82 (the largest cutoff of the table).
+ */
+int32_t chase_nex_linear(int32_t nex_low, int32_t nex_high, double e_low, double e_high,
+                         double e);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching of independent eigenproblems on one GPU (no source

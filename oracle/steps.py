@@ -248,3 +248,16 @@ def lock_count(res, tol_abs):
         else:
             break
     return n
+
+
+# --------------------------------------------------------------------------
+# nex across a series of matrices (supplement, Eq. S2)
+# --------------------------------------------------------------------------
+
+def nex_linear(nex_low, nex_high, e_low, e_high, e):
+    """nex for energy cutoff e on the straight line through (e_low, nex_low)
+    and (e_high, nex_high), rounded to the nearest integer with halves away
+    from zero, never below 0."""
+    v = nex_low + (nex_high - nex_low) / (e_high - e_low) * (e - e_low)
+    r = math.floor(abs(v) + 0.5)
+    return max(0, r if v >= 0 else -r)

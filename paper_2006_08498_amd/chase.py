@@ -58,6 +58,8 @@ class ChaseOpts(ctypes.Structure):
         ("graphs", ctypes.c_int32),
         ("on_iteration", ctypes.c_void_p),
         ("on_iteration_user", ctypes.c_void_p),
+        ("v0_cols", ctypes.c_int32),
+        ("out_cols", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 2),
     ]
 
@@ -140,6 +142,7 @@ SIGNATURES = {
     "chase_residuals": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _P, _P]),
     "chase_heevj": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "chase_degrees": (ctypes.c_int, [_P, _P, _I32, _D, _D, _D, _I32, _I32, _P]),
+    "chase_nex_linear": (_I32, [_I32, _I32, _D, _D, _D]),
 }
 
 
@@ -233,14 +236,17 @@ ITER_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ChaseIn
 
 
 def solve(H, nev, nex, tol=1e-10, degree_max=20, *, opts=None, V0=None,
-          workspace=None, stream=None, allow_noconv=False, on_iteration=None, **opt_kw):
+          workspace=None, stream=None, allow_noconv=False, on_iteration=None,
+          out_cols=None, **opt_kw):
     """Lowest ``nev`` eigenpairs of the Hermitian CUDA tensor ``H``.
 
     Returns eigenvalues (ascending), eigenvectors as an (N, nev) tensor,
     residual norms, the status and the solver's info record.
     ``on_iteration(info_dict)`` is called after every subspace iteration; a
     true return value stops the solve there (status CHASE_ENOCONV unless nev
-    pairs are locked)."""
+    pairs are locked).  ``V0`` (N, k) with k <= nev + nex warm-starts the
+    solve; ``out_cols`` (nev..nev+nex) returns that many columns of the final
+    search block, the warm start of the next matrix of a sequence."""
     torch = _torch()
     N = H.shape[0]
     hp, ldh, conj = _h_layout(H)
@@ -259,9 +265,13 @@ def solve(H, nev, nex, tol=1e-10, degree_max=20, *, opts=None, V0=None,
         # Warm start, N x (nev+nex): the ABI wants it column-major (and
         # conjugated when H is passed row-major, i.e. as conj(H)).
         v0 = V0.conj() if conj else V0
-        v0_keep = v0.t().contiguous()       # (ne, N) row-major == col-major
+        v0_keep = v0.t().contiguous()       # (k, N) row-major == col-major
         o.dV0 = v0_keep.data_ptr()
-    out = torch.empty((nev, N), dtype=torch.complex128, device=H.device)
+        o.v0_cols = v0_keep.shape[0]
+    if out_cols is not None:
+        o.out_cols = out_cols
+    mout = o.out_cols if o.out_cols > 0 else nev
+    out = torch.empty((mout, N), dtype=torch.complex128, device=H.device)
     ev = np.zeros(nev, dtype=np.float64)
     rs = np.zeros(nev, dtype=np.float64)
     info = ChaseInfo()
@@ -455,6 +465,14 @@ def degrees(theta, resid, tol_abs, alpha, beta, degree_max, extra=2):
                                tol_abs, alpha, beta, degree_max, extra,
                                out.ctypes.data_as(_P)))
     return out
+
+
+def nex_linear(nex_low, nex_high, e_low, e_high, e):
+    """Supplement Eq. S2: nex interpolated linearly in the energy cutoff."""
+    v = lib().chase_nex_linear(nex_low, nex_high, e_low, e_high, e)
+    if v < 0:
+        raise ChaseError(CHASE_EINVAL, last_error())
+    return v
 
 
 # ------------------------------------------------------------------ serving

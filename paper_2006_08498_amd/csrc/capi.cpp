@@ -146,6 +146,10 @@ int chase_solve_ex(const chase_z *dH, int64_t N, int64_t ldh, int32_t nev,
         REQUIRE(ldv >= N, "ldv must be >= N");
         const chase_opts opts = resolve(o);
         validate_opts(opts);
+        REQUIRE(opts.v0_cols >= 0 && opts.v0_cols <= nev + nex,
+                "v0_cols must be in [0, nev + nex]");
+        REQUIRE(opts.out_cols == 0 || (opts.out_cols >= nev && opts.out_cols <= nev + nex),
+                "out_cols must be 0 or in [nev, nev + nex]");
         const Layout lay = make_layout(N, nev, nex, opts);
         hipStream_t s = S(stream);
         DevBuf own(dwork ? 0 : lay.total, s);
@@ -492,6 +496,20 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
         CHASE_HIP(hipStreamSynchronize(s));
         return CHASE_OK;
     });
+}
+
+int32_t chase_nex_linear(int32_t nex_low, int32_t nex_high, double e_low, double e_high,
+                         double e) {
+    int32_t out = -1;
+    const int st = guarded([&]() -> int {
+        REQUIRE(nex_low >= 0 && nex_high >= 0, "nex_low and nex_high must be >= 0");
+        REQUIRE(std::isfinite(e_low) && std::isfinite(e_high) && std::isfinite(e),
+                "energies must be finite");
+        REQUIRE(e_high > e_low, "e_high must be > e_low");
+        out = nex_linear(nex_low, nex_high, e_low, e_high, e);
+        return CHASE_OK;
+    });
+    return st == CHASE_OK ? out : -1;
 }
 
 int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,

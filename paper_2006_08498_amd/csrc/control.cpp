@@ -120,4 +120,10 @@ int degree_for(double res, double tol_abs, double lam, double c, double e,
     return d + (d % 2);   // cap is even, so this stays <= cap
 }
 
+int nex_linear(int nex_low, int nex_high, double e_low, double e_high, double e) {
+    const double slope = (double)(nex_high - nex_low) / (e_high - e_low);
+    const double v = std::round((double)nex_low + slope * (e - e_low));
+    return (int)std::max(0.0, std::min(v, 2147483647.0));
+}
+
 }  // namespace chase

@@ -26,4 +26,9 @@ int degree_cap(int degree_max);
 int degree_for(double res, double tol_abs, double lam, double c, double e,
                int degree_max, int extra);
 
+// Supplement Eq. S2: nex interpolated linearly in the energy cutoff between
+// (e_low, nex_low) and (e_high, nex_high), rounded half away from zero, at
+// least 0.  Requires e_high > e_low.
+int nex_linear(int nex_low, int nex_high, double e_low, double e_high, double e);
+
 }  // namespace chase

@@ -373,7 +373,10 @@ int submit_common(chase_server *s, std::unique_ptr<Request> r, uint64_t *ticket)
         return srv_fail(CHASE_EINVAL, "bad tol / degree_max");
     if (r->opts.precision != CHASE_FP64 && r->opts.precision != CHASE_MIXED)
         return srv_fail(CHASE_EINVAL, "unknown precision");
-    if (r->opts.dV0) return srv_fail(CHASE_EINVAL, "warm start is not supported by the server");
+    if (r->opts.dV0 || r->opts.v0_cols != 0)
+        return srv_fail(CHASE_EINVAL, "warm start is not supported by the server");
+    if (r->opts.out_cols != 0 && r->opts.out_cols != r->nev)
+        return srv_fail(CHASE_EINVAL, "the server returns nev columns (out_cols must be 0)");
     r->footprint = footprint(*r);
     if (r->footprint > s->budget)
         return srv_fail(CHASE_ENOMEM, "request footprint " + std::to_string(r->footprint) +

@@ -453,7 +453,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
 
     // ---------------- start block
     if (o.dV0) {
-        const int given = p.nev + p.nex;
+        const int given = o.v0_cols > 0 ? o.v0_cols : p.nev + p.nex;
         colmajor_to_rowmajor(reinterpret_cast<const Z *>(o.dV0), N, V, ne, N, given, s);
         if (ne > given) random_block(V + given, ne, N, ne - given, o.seed, 2u, s);
     } else {
@@ -476,7 +476,10 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     // Residual of each Ritz position at the previous iteration, and the
     // whole-block refinement state (see the stagnation test below).
     std::vector<double> res_last(ne, INFINITY);
-    bool refine = false;
+    // A warm start begins with a Rayleigh-Ritz of the given block, no
+    // filter: its residuals choose the first degrees (converged pairs lock
+    // at once) and its largest Ritz value the first damped interval.
+    bool refine = o.dV0 != nullptr;
     int last_refine = -100;
     int L = 0;
     int it = 0;
@@ -649,18 +652,23 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     R.status = L >= nev ? CHASE_OK : CHASE_ENOCONV;
 
     // ---------------- output: the nev lowest, ascending, phase-normalised
-    std::vector<int> ord(nev);
+    // Columns past nev (out_cols) continue with the rest of the search
+    // block, sorted among themselves.
+    const int mout = o.out_cols > 0 ? o.out_cols : nev;
+    std::vector<int> ord(mout);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    auto by_lam = [&](int a, int b) { return lam[a] < lam[b]; };
+    std::stable_sort(ord.begin(), ord.begin() + nev, by_lam);
+    std::stable_sort(ord.begin() + nev, ord.end(), by_lam);
     R.eigvals.resize(nev);
     R.resid.resize(nev);
     for (int j = 0; j < nev; ++j) {
         R.eigvals[j] = lam[ord[j]];
         R.resid[j] = res[ord[j]];
     }
-    CHASE_HIP(hipMemcpyAsync(perm, ord.data(), sizeof(int) * nev, hipMemcpyHostToDevice, s));
-    permute_cols(V, ne, B1, nev, N, nev, perm, s);
-    phase_normalise_out(B1, nev, N, nev, dV, ldv, npart, s);
+    CHASE_HIP(hipMemcpyAsync(perm, ord.data(), sizeof(int) * mout, hipMemcpyHostToDevice, s));
+    permute_cols(V, ne, B1, mout, N, mout, perm, s);
+    phase_normalise_out(B1, mout, N, mout, dV, ldv, npart, s);
     CHASE_HIP(hipStreamSynchronize(s));
     info.filter_flops = 8.0 * (double)N * (double)N * (double)info.matvecs_filter;
     if (o.profile) {

@@ -91,6 +91,20 @@ def test_mixed_precision_flag_validated():
     assert st == chase.CHASE_EINVAL
 
 
+@pytest.mark.parametrize("kw,msg", [
+    (dict(v0_cols=-1), "v0_cols"), (dict(v0_cols=4), "v0_cols"),
+    (dict(out_cols=1), "out_cols"), (dict(out_cols=4), "out_cols"),
+])
+def test_sequence_columns_validated(kw, msg):
+    L = chase.lib()
+    o = chase.default_opts(**kw)
+    ev = np.zeros(2)
+    st = L.chase_solve_ex(ctypes.c_void_p(16), 10, 10, 2, 1, 1e-10, 20,
+                          ev.ctypes.data_as(ctypes.c_void_p), None, ctypes.c_void_p(16),
+                          10, None, 0, None, ctypes.byref(o), None)
+    assert st == chase.CHASE_EINVAL and msg in chase.last_error()
+
+
 def test_workspace_bytes():
     a = chase.workspace_bytes(2000, 20, 10)
     b = chase.workspace_bytes(4000, 20, 10)
@@ -137,3 +151,17 @@ def test_group_and_server_arguments_rejected_without_device_work():
     assert L.chase_server_create(0, 2, 8) is None
     assert b"flags" in L.chase_server_last_error()
     assert L.chase_server_create(0, 0, 0) is None
+
+
+def test_nex_linear_matches_oracle_and_rejects_bad_input():
+    from oracle import steps
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        lo, hi = (int(v) for v in rng.integers(0, 400, 2))
+        e0 = float(rng.uniform(-5, 20))
+        e1 = e0 + float(rng.uniform(0.01, 10))
+        e = float(rng.uniform(e0 - 3, e1 + 3))
+        assert chase.nex_linear(lo, hi, e0, e1, e) == steps.nex_linear(lo, hi, e0, e1, e)
+    for bad in [(-1, 5, 0.0, 1.0, 0.5), (1, 5, 1.0, 1.0, 0.5), (1, 5, 0.0, float("nan"), 0.5)]:
+        with pytest.raises(chase.ChaseError):
+            chase.nex_linear(*bad)

@@ -1,0 +1,79 @@
+"""Sequences of eigenproblems through the C ABI: warm starts from the
+previous solve's search block (chase_opts.dV0 / v0_cols / out_cols), each
+solve against the oracle's dense eigendecomposition of its own matrix."""
+import numpy as np
+import pytest
+
+from oracle import eig
+from paper_2006_08498_amd import chase, synth
+from tests.gpu_util import dev_colmajor, host, torch_cuda
+from tests.test_gpu_solve import _check_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _series(N, T, delta, seed=0):
+    """H_t = H_0 + t * delta * P: a D + K matrix moved along a fixed
+    Hermitian direction P (another D + K draw), t = 0 .. T-1."""
+    H0 = synth.dk_matrix(N, seed=seed)
+    P = synth.dk_matrix(N, seed=seed + 100)
+    return [H0 + (t * delta) * P for t in range(T)]
+
+
+@pytest.mark.parametrize("precision", [chase.CHASE_FP64, chase.CHASE_MIXED])
+def test_warm_chain_matches_oracle_and_saves_filter_work(precision):
+    torch = torch_cuda()
+    N, nev, nex = 1500, 20, 10
+    Hs = _series(N, 4, 1e-4)
+    V = None
+    warm, cold = [], []
+    for t, H in enumerate(Hs):
+        print(f"sequence t={t} precision={precision}", flush=True)
+        dH = dev_colmajor(H)
+        kw = dict(precision=precision)
+        if V is not None:
+            kw.update(lanczos_steps=10, lanczos_runs=1)
+        r = chase.solve(dH, nev, nex, V0=V, out_cols=nev + nex, **kw)
+        assert r.status == chase.CHASE_OK
+        assert r.V.shape == (N, nev + nex)
+        head = chase.SolveResult(r.eigvals, r.V[:, :nev], r.resid, r.status, r.info)
+        _check_against_oracle(H, head, nev)
+        c = chase.solve(dH, nev, nex, precision=precision)
+        assert np.abs(r.eigvals - c.eigvals).max() <= 1e-10 * np.abs(c.eigvals).max()
+        if t > 0:
+            warm.append(r.info["matvecs_filter"])
+            cold.append(c.info["matvecs_filter"])
+        V = r.V
+        del dH
+    # A step of 1e-4 ||P|| leaves residuals near 1e-4 instead of O(1): the
+    # warm solves need well under the cold solves' filter work.
+    assert sum(warm) < 0.75 * sum(cold), (warm, cold)
+
+
+def test_out_cols_extends_the_default_output_bitwise():
+    torch_cuda()
+    N, nev, nex = 1200, 16, 8
+    H = synth.dk_matrix(N, seed=3)
+    dH = dev_colmajor(H)
+    a = chase.solve(dH, nev, nex)
+    b = chase.solve(dH, nev, nex, out_cols=nev + nex)
+    assert np.array_equal(a.eigvals, b.eigvals) and np.array_equal(a.resid, b.resid)
+    Va, Vb = host(a.V), host(b.V)
+    assert np.array_equal(Va, Vb[:, :nev])
+    assert np.abs(Vb.conj().T @ Vb - np.eye(nev + nex)).max() <= 1e-12
+    # The extra columns are Ritz vectors of the rest of the search block,
+    # by ascending Rayleigh quotient, all above the wanted eigenvalues.
+    q = np.real(np.einsum("ij,ij->j", Vb.conj(), H @ Vb))[nev:]
+    assert np.all(np.diff(q) >= -1e-12) and q[0] >= a.eigvals[-1] - 1e-12
+    mid = chase.solve(dH, nev, nex, out_cols=nev + 3)
+    assert np.array_equal(host(mid.V), Vb[:, :nev + 3])
+
+
+def test_partial_warm_start_fills_the_rest_randomly():
+    torch = torch_cuda()
+    N, nev, nex = 1000, 12, 6
+    H = synth.dk_matrix(N, seed=5)
+    w, V = eig.eigh_lowest(H, nev)
+    r = chase.solve(dev_colmajor(H), nev, nex, V0=torch.from_numpy(V).cuda())
+    assert r.status == chase.CHASE_OK and r.info["iterations"] <= 3
+    _check_against_oracle(H, r, nev)

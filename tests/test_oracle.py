@@ -17,8 +17,8 @@ from paper_2006_08498_amd import synth
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _rows():
-    with open(os.path.join(GOLDEN, "eq_s1_tables.csv")) as f:
+def _rows(name="eq_s1_tables.csv"):
+    with open(os.path.join(GOLDEN, name)) as f:
         lines = [ln for ln in f if not ln.startswith("#")]
     return list(csv.reader(lines))
 
@@ -273,3 +273,27 @@ def test_residual_of_two_eigenvector_mix():
 def test_lock_count_prefix_only():
     assert steps.lock_count([1e-12, 1e-11, 1e-3, 1e-12], 1e-10) == 2
     assert steps.lock_count([1e-3, 1e-12], 1e-10) == 0
+
+
+# ---------------------------------------------------------------- Eq. S2
+
+def test_eq_s2_reproduces_table_s10_with_upper_cutoff_14_32():
+    # Reading of the garbled Eq. S2: Table S10 follows from the printed
+    # formula only with E_cut-high = 14.32 eV (the printed 12.82 is the
+    # largest cutoff of the table, where the formula would give nex_high).
+    rows = _rows("table_s10.csv")
+    assert len(rows) == 5
+    for nodes, ecut, n100, n150 in rows:
+        e = float(ecut)
+        assert steps.nex_linear(40, 100, 10.54, 14.32, e) == int(n100), nodes
+        assert steps.nex_linear(40, 150, 10.54, 14.32, e) == int(n150), nodes
+    # with the printed 12.82 the last row would be nex_high itself
+    assert steps.nex_linear(40, 100, 10.54, 12.82, 12.82) == 100 != int(rows[-1][2])
+
+
+def test_eq_s2_endpoints_rounding_and_floor():
+    assert steps.nex_linear(25, 100, 1.0, 2.0, 1.0) == 25
+    assert steps.nex_linear(25, 100, 1.0, 2.0, 2.0) == 100
+    assert steps.nex_linear(0, 1, 0.0, 2.0, 1.0) == 1          # 0.5 rounds up
+    assert steps.nex_linear(10, 0, 0.0, 1.0, 3.0) == 0         # extrapolation floored at 0
+    assert steps.nex_linear(10, 20, 0.0, 1.0, 1.5) == 25       # extrapolates above
