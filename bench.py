@@ -357,6 +357,121 @@ def kernel_roofline(infos, N, workload):
     return S, roof, phase_roof, phases, ach64, ach32
 
 
+INGEST = dict(N=24000, std=0.02, decay=200.0)
+PCIE_PEAK_GBS = 64.0       # PCIe 5.0 x16, one direction (published)
+
+
+def run_ingest(args):
+    """H from row stripes of its lower triangle: host rows streamed through
+    the device (the whole job), and the two HBM-bound kernels alone."""
+    import torch
+    from paper_2006_08498_amd import chase, synth
+    N = INGEST["N"]
+    log(f"workload ingest24k: generating N={N} on the device")
+    H = synth.dk_matrix_device(N, seed=args.seed, std=INGEST["std"], decay=INGEST["decay"])
+    rows_h = torch.empty((N, N), dtype=torch.complex128, pin_memory=True)
+    rows_h.copy_(H)                                  # row-major, page-locked
+    rows_d = H.contiguous()                          # row-major on the device
+    H2 = torch.empty((N, N), dtype=torch.complex128, device="cuda").t()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    bits = lambda X: torch.view_as_real(X).view(torch.int64)
+
+    for _ in range(args.warmup):
+        chase.ingest_rows(H2, rows_h, 0, stream=s)
+    t_host = []
+    for _ in range(args.steps):
+        H2.fill_(float("nan"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chase.ingest_rows(H2, rows_h, 0, stream=s)   # returns when done
+        t_host.append(time.perf_counter() - t0)
+    ok_host = torch.equal(bits(H2), bits(H))
+
+    def kernel_ms(call):
+        ts = []
+        for _ in range(args.warmup):
+            call()
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            call()
+            b.record(s)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.mean(ts))
+
+    H2.fill_(float("nan"))
+    torch.cuda.synchronize()
+    ms_rows = kernel_ms(lambda: chase.ingest_rows(H2, rows_d, 0, stream=s))
+    ok_dev = torch.equal(bits(H2), bits(H))
+    H2.copy_(torch.tril(H))
+    torch.cuda.synchronize()
+    ms_comp = kernel_ms(lambda: chase.hermitian_complete(H2, "L", stream=s))
+    ok_comp = torch.equal(bits(H2), bits(H))
+    by_rows = 24.0 * N * N + 8.0 * N                 # read the lower half, write both
+    by_comp = 16.0 * N * N + 16.0 * N                # read one half, write the other
+    host_bytes = 8.0 * N * (N + 1)                   # the lower triangle
+    per = float(np.median(t_host))
+    ach = by_rows / (ms_rows * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_ingest_rows (row stripes into both triangles)",
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "launches": 1, "avg_launch_ms": ms_rows,
+            "algorithmic_bytes_per_launch": by_rows}
+    from paper_2006_08498_amd import profsum
+    rec = profsum.read_record(os.path.join(ROOT, "profiles", "k_ingest_rows_ingest24k.md"))
+    if rec and rec.get("sources_digest") == profsum.sources_digest("k_ingest_rows") \
+            and rec.get("workload") == "ingest24k":
+        roof["traffic"] = rec["bytes_per_launch"]
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, " \
+                               "copy-calibrated)"
+    out = {
+        "metric": METRIC,
+        "value_is": "time to build H on the device from page-locked host row stripes of its "
+                    "lower triangle (s per matrix); the solve's input step",
+        "value": per, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": per * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"ingest24k: D+K N={N} lower-triangle row stripes -> "
+                               f"column-major Hermitian H", "N": N, "parallelism": "1 GPU"},
+        "host_gbs": host_bytes / per / 1e9,
+        "host_frac_of_pcie": host_bytes / per / 1e9 / PCIE_PEAK_GBS,
+        "kernels": {
+            "k_ingest_rows": {"ms": ms_rows, "bytes": by_rows,
+                              "gbs": ach, "frac": ach / HBM_PEAK_GBS},
+            "k_herm_complete": {"ms": ms_comp, "bytes": by_comp,
+                                "gbs": by_comp / (ms_comp * 1e-3) / 1e9,
+                                "frac": by_comp / (ms_comp * 1e-3) / 1e9 / HBM_PEAK_GBS}},
+        "check": {"host_bitwise": ok_host, "device_bitwise": ok_dev,
+                  "complete_bitwise": ok_comp},
+        "roofline": roof,
+    }
+    log(f"ingest: host {per:.3f} s ({out['host_gbs']:.1f} GB/s), rows kernel {ms_rows:.2f} ms "
+        f"({ach:.0f} GB/s), complete {ms_comp:.2f} ms; checks {out['check']}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = ingest_cpu_baseline(N, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def ingest_cpu_baseline(N, budget_s):
+    """The oracle's completion of the lower triangle on a host sample whose
+    time fits the budget, scaled by (N / N_s)^2."""
+    from oracle import steps
+    rng = np.random.default_rng(0)
+    ns = 1000
+    while True:
+        A = rng.standard_normal((ns, ns)) + 1j * rng.standard_normal((ns, ns))
+        t0 = time.perf_counter()
+        steps.hermitian_from_triangle(A, lower=True)
+        t = time.perf_counter() - t0
+        if t * 4.0 > budget_s or ns * 2 > N:
+            break
+        ns *= 2
+    return {"value": t * (N / ns) ** 2, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle completion (numpy, one thread) of one N={ns} lower "
+                      f"triangle took {t:.2f} s; scaled by (N/{ns})^2 to N={N}"}
+
+
 def run_sequence(args):
     """Warm-started chain against cold solves of the same matrices."""
     import torch
@@ -456,7 +571,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="planted24k",
-                    choices=sorted(WORKLOADS) + ["serve128", "seq24k"])
+                    choices=sorted(WORKLOADS) + ["serve128", "seq24k", "ingest24k"])
     ap.add_argument("--slots", type=int, default=6, help="serve128: concurrent solves")
     ap.add_argument("--fuse", type=int, default=0,
                     help="serve128: fuse concurrent solves' filter steps (1) or not (0)")
@@ -512,6 +627,9 @@ def main():
         return
     if args.workload == "seq24k":
         run_sequence(args)
+        return
+    if args.workload == "ingest24k":
+        run_ingest(args)
         return
 
     w = WORKLOADS[args.workload]

@@ -365,6 +365,48 @@ int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
 int32_t chase_nex_linear(int32_t nex_low, int32_t nex_high, double e_low, double e_high,
                          double e);
 
+/* ------------------------------------------------------------ ingesting H
+ * The paper reads H as stripes of rows of its lower half and then fills the
+ * upper half from the ranks holding the transposed parts (Sec. "Matrix
+ * generation and the I/O challenge").  These calls build the column-major
+ * Hermitian H that the solve calls read from such stripes, or complete H in
+ * place from one stored triangle.  The result is Hermitian to the last bit
+ * with a real diagonal (the imaginary part of a stored diagonal entry is
+ * dropped).  All require 1 <= N <= 180000 and ldh >= N.
+ */
+
+/*
+ * Rows [r0, r0 + nrows) of the lower triangle, row-major in device memory:
+ * row r at dRows + (r - r0)*ldr, of which columns 0..r are read (entries
+ * right of the diagonal are never read).  Writes H(r, c) and
+ * H(c, r) = conj(H(r, c)) for c < r, and H(r, r) = its real part.  Stripes
+ * may come in any order; once they cover rows 0..N-1, dH is complete.
+ * Requires r0 >= 0, nrows >= 0, r0 + nrows <= N, ldr >= r0 + nrows, dH and
+ * dRows not NULL when nrows > 0; dRows must not overlap dH.
+ */
+int chase_ingest_rows(chase_z *dH, int64_t N, int64_t ldh, const chase_z *dRows,
+                      int64_t ldr, int64_t r0, int64_t nrows, void *stream);
+
+/*
+ * The same from host memory hRows (same layout), streamed in chunks of rows
+ * through two device staging buffers that the call allocates (about 64 MiB
+ * each) and frees: the host-to-device copy of one chunk, on a stream of the
+ * call's own, overlaps the ingestion of the previous chunk on `stream`.
+ * Page-locked hRows (hipHostMalloc, torch pin_memory) moves at the PCIe
+ * rate; pageable memory works, more slowly.  CHASE_ENOMEM if the staging
+ * buffers cannot be allocated.
+ */
+int chase_ingest_rows_host(chase_z *dH, int64_t N, int64_t ldh, const chase_z *hRows,
+                           int64_t ldr, int64_t r0, int64_t nrows, void *stream);
+
+/*
+ * H in place from its lower (uplo = 'L') or upper (uplo = 'U') triangle,
+ * diagonal included: the other strict triangle becomes the conjugate
+ * transpose and the diagonal's imaginary part 0.
+ */
+int chase_hermitian_complete(chase_z *dH, int64_t N, int64_t ldh, int32_t uplo,
+                             void *stream);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of independent eigenproblems on one GPU (no source
  * in the paper, which solves one matrix at a time; its workflows solve

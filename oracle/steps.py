@@ -261,3 +261,30 @@ def nex_linear(nex_low, nex_high, e_low, e_high, e):
     v = nex_low + (nex_high - nex_low) / (e_high - e_low) * (e - e_low)
     r = math.floor(abs(v) + 0.5)
     return max(0, r if v >= 0 else -r)
+
+
+# --------------------------------------------------------------------------
+# Ingesting H: the Hermitian matrix from one stored triangle (main text,
+# Sec. "Matrix generation and the I/O challenge": the lower half is read,
+# the upper half filled from the transposed parts)
+# --------------------------------------------------------------------------
+
+def hermitian_from_triangle(A, lower=True):
+    """The Hermitian matrix whose stored triangle (lower or upper, diagonal
+    included) is A's: each element of the other strict triangle is the
+    conjugate of its mirror, and the diagonal keeps its real part.  Written
+    element by element so that every value is a copy (or a sign flip) of
+    A's, bit for bit."""
+    A = np.asarray(A, dtype=np.complex128)
+    N = A.shape[0]
+    C = np.empty((N, N), dtype=np.complex128)
+    i, j = np.tril_indices(N, -1)          # i > j
+    if lower:
+        C[i, j] = A[i, j]
+        C[j, i] = np.conj(A[i, j])
+    else:
+        C[j, i] = A[j, i]
+        C[i, j] = np.conj(A[j, i])
+    d = np.arange(N)
+    C[d, d] = A[d, d].real.astype(np.complex128)
+    return C

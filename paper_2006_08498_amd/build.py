@@ -26,7 +26,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_filter32.hip", "k_blas.hip", "k_dense.hip",
-           "control.cpp", "solver.cpp", "capi.cpp", "server.cpp"]
+           "k_ingest.hip", "control.cpp", "solver.cpp", "capi.cpp", "server.cpp"]
 # Input generators live in a library of their own: they are not the solver.
 SYNTH_SOURCES = ["synth_dev.hip"]
 

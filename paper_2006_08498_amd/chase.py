@@ -143,6 +143,9 @@ SIGNATURES = {
     "chase_heevj": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "chase_degrees": (ctypes.c_int, [_P, _P, _I32, _D, _D, _D, _I32, _I32, _P]),
     "chase_nex_linear": (_I32, [_I32, _I32, _D, _D, _D]),
+    "chase_ingest_rows": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _I64, _P]),
+    "chase_ingest_rows_host": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _I64, _P]),
+    "chase_hermitian_complete": (ctypes.c_int, [_P, _I64, _I64, _I32, _P]),
 }
 
 
@@ -465,6 +468,37 @@ def degrees(theta, resid, tol_abs, alpha, beta, degree_max, extra=2):
                                tol_abs, alpha, beta, degree_max, extra,
                                out.ctypes.data_as(_P)))
     return out
+
+
+# ------------------------------------------------------------ ingesting H
+
+def ingest_rows(H, rows, r0, stream=None):
+    """Rows [r0, r0 + len(rows)) of the lower triangle of H (row r has its
+    columns 0..r in rows[r - r0]) into the column-major device matrix H, both
+    triangles.  ``rows`` is a row-major complex128 block: a CUDA tensor, or
+    host memory (a CPU tensor or numpy array; page-locked moves fastest),
+    which is streamed to the device in chunks."""
+    hp, ldh = _h_colmajor(H)
+    N = H.shape[0]
+    if isinstance(rows, np.ndarray):
+        if rows.dtype != np.complex128 or rows.ndim != 2 or rows.strides[1] != 16 \
+                or rows.strides[0] % 16:
+            raise ValueError("rows must be a row-major complex128 array")
+        ptr, ldr, on_dev = rows.ctypes.data, rows.strides[0] // 16, False
+    else:
+        torch = _torch()
+        if rows.dtype != torch.complex128 or rows.dim() != 2 or rows.stride(1) != 1:
+            raise ValueError("rows must be a row-major complex128 tensor")
+        ptr, ldr, on_dev = rows.data_ptr(), rows.stride(0), rows.is_cuda
+    fn = lib().chase_ingest_rows if on_dev else lib().chase_ingest_rows_host
+    _check(fn(hp, N, ldh, ptr, ldr, r0, rows.shape[0], _stream_ptr(stream)))
+
+
+def hermitian_complete(H, uplo="L", stream=None):
+    """Complete the column-major device matrix H in place from its lower
+    ('L') or upper ('U') triangle."""
+    hp, ldh = _h_colmajor(H)
+    _check(lib().chase_hermitian_complete(hp, H.shape[0], ldh, ord(uplo), _stream_ptr(stream)))
 
 
 def nex_linear(nex_low, nex_high, e_low, e_high, e):

@@ -498,6 +498,52 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
     });
 }
 
+static void validate_ingest(const chase_z *dH, int64_t N, int64_t ldh, const chase_z *rows,
+                            int64_t ldr, int64_t r0, int64_t nrows) {
+    REQUIRE(N >= 1 && N <= 180000, "N must be in [1, 180000]");
+    REQUIRE(ldh >= N, "ldh must be >= N");
+    REQUIRE(r0 >= 0 && nrows >= 0 && r0 + nrows <= N, "need r0 >= 0, nrows >= 0, r0 + nrows <= N");
+    REQUIRE(ldr >= r0 + nrows, "ldr must be >= r0 + nrows");
+    REQUIRE(nrows == 0 || (dH && rows), "NULL pointer");
+}
+
+int chase_ingest_rows(chase_z *dH, int64_t N, int64_t ldh, const chase_z *dRows, int64_t ldr,
+                      int64_t r0, int64_t nrows, void *stream) {
+    return guarded([&]() -> int {
+        validate_ingest(dH, N, ldh, dRows, ldr, r0, nrows);
+        if (nrows == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        ingest_rows(reinterpret_cast<Z *>(dH), ldh, reinterpret_cast<const Z *>(dRows), ldr, r0,
+                    nrows, s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
+int chase_ingest_rows_host(chase_z *dH, int64_t N, int64_t ldh, const chase_z *hRows,
+                           int64_t ldr, int64_t r0, int64_t nrows, void *stream) {
+    return guarded([&]() -> int {
+        validate_ingest(dH, N, ldh, hRows, ldr, r0, nrows);
+        if (nrows == 0) return CHASE_OK;
+        ingest_rows_host(reinterpret_cast<Z *>(dH), ldh, reinterpret_cast<const Z *>(hRows),
+                         ldr, r0, nrows, S(stream));
+        return CHASE_OK;
+    });
+}
+
+int chase_hermitian_complete(chase_z *dH, int64_t N, int64_t ldh, int32_t uplo, void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(N >= 1 && N <= 180000, "N must be in [1, 180000]");
+        REQUIRE(ldh >= N, "ldh must be >= N");
+        REQUIRE(uplo == 'L' || uplo == 'U', "uplo must be 'L' or 'U'");
+        REQUIRE(dH != nullptr, "dH is NULL");
+        hipStream_t s = S(stream);
+        hermitian_complete(reinterpret_cast<Z *>(dH), ldh, N, uplo == 'L', s);
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
 int32_t chase_nex_linear(int32_t nex_low, int32_t nex_high, double e_low, double e_high,
                          double e) {
     int32_t out = -1;

@@ -71,6 +71,21 @@ struct FilterCall {
 // so its result is bitwise the same as a filter_gemm call.
 void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s);
 
+// Ingesting H (k_ingest.hip).  ingest_rows: rows [r0, r0 + nrows) of the
+// lower triangle, row-major in device memory (row r at rows + (r - r0)*ldr,
+// columns 0..r read), written into both triangles of the column-major H with
+// a real diagonal.  ingest_rows_host: the same from host memory, streamed
+// through two device staging buffers of ingest_chunk_rows() rows so that the
+// copy of one chunk overlaps the kernel of the previous; returns after the
+// work on s is done.  hermitian_complete: H in place from its lower (or
+// upper) triangle.
+void ingest_rows(Z *H, int64_t ldh, const Z *rows, int64_t ldr, int64_t r0, int64_t nrows,
+                 hipStream_t s);
+int64_t ingest_chunk_rows(int64_t r0, int64_t nrows);
+void ingest_rows_host(Z *H, int64_t ldh, const Z *hrows, int64_t ldr, int64_t r0, int64_t nrows,
+                      hipStream_t s);
+void hermitian_complete(Z *H, int64_t ldh, int64_t N, bool lower, hipStream_t s);
+
 // FP32 filter GEMM on the complex64 shadow Hc (mixed precision), same
 // contract as filter_gemm; partials: filter32_partial_elems(N, n) complex64.
 void filter32_gemm(const C *H, int64_t ldh, int64_t N, const C *Y, int64_t ldy,

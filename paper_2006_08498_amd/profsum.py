@@ -4,12 +4,18 @@
     python -m paper_2006_08498_amd.profsum traffic --fetch D --write D \
         --copy-fetch D --copy-write D --copy-bytes B [--match SUBSTR] [--workload W]
     python -m paper_2006_08498_amd.profsum counters DIR [--match SUBSTR]
+    python -m paper_2006_08498_amd.profsum trace DIR [--match SUBSTR] [--last K]
     python -m paper_2006_08498_amd.profsum bandwidth --trace D --fetch D --write D \
         --copy-fetch D --copy-write D --copy-bytes B [--match A,B,...]
 
 `stats` prints the rows of the kernel-statistics CSV under DIR (from
 `rocprofv3 --kernel-trace --stats --output-format csv`) whose kernel name
 contains SUBSTR, plus their call-weighted average duration.
+
+`trace` prints each matching kernel's average dispatch duration from a
+kernel trace (`--kernel-trace --output-format csv`); `--last K` keeps each
+kernel's last K dispatches only (here and in `traffic`), which singles out
+the launches a benchmark times when the same kernel also ran before them.
 
 `counters` prints, per kernel, the mean per dispatch of every counter of
 a `--pmc` run (for instance MfmaUtil, the percentage of cycles the MFMA
@@ -46,6 +52,8 @@ CSRC = os.path.join(HERE, "csrc")
 KERNEL_SOURCES = {
     "k_filter": ("k_filter_kern.h", "k_filter.hip", "k_filter_wide.hip", "k_filter_plan.h"),
     "k_filter32": ("k_filter32.hip", "k_filter_plan.h"),
+    "k_ingest_rows": ("k_ingest.hip",),
+    "k_herm_complete": ("k_ingest.hip",),
 }
 
 
@@ -72,14 +80,36 @@ def kernel_stats(d, match):
     return rows
 
 
-def counter_values(d, match, counter):
-    """Per-dispatch values of `counter` for kernels whose name contains match."""
+def counter_values(d, match, counter, last=0):
+    """Per-dispatch values of `counter` for kernels whose name contains match
+    (with last > 0: only each kernel's last `last` dispatches, by dispatch
+    id)."""
     per = collections.defaultdict(list)
     for f in _csvs(d, "counter_collection.csv"):
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] == counter and match in r["Kernel_Name"]:
-                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-    return per
+                per[r["Kernel_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    out = {}
+    for name, v in per.items():
+        v.sort()
+        out[name] = [x for _, x in (v[-last:] if last > 0 else v)]
+    return out
+
+
+def trace_durations(d, match, last=0):
+    """Per-dispatch durations (ns) from a kernel trace, per kernel name, in
+    dispatch order (with last > 0: each kernel's last `last` dispatches)."""
+    per = collections.defaultdict(list)
+    for f in _csvs(d, "kernel_trace.csv"):
+        for r in csv.DictReader(open(f)):
+            if match in r["Kernel_Name"]:
+                per[r["Kernel_Name"]].append(
+                    (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for name, v in per.items():
+        v.sort()
+        out[name] = [x for _, x in (v[-last:] if last > 0 else v)]
+    return out
 
 
 def _short(name):
@@ -110,8 +140,8 @@ def cmd_traffic(a):
         sys.exit("copy-kernel counters missing")
     kf = a.copy_bytes / (cf_mean * 1024.0)
     kw = a.copy_bytes / (cw_mean * 1024.0)
-    fv = counter_values(a.fetch, a.match, "FETCH_SIZE")
-    wv = counter_values(a.write, a.match, "WRITE_SIZE")
+    fv = counter_values(a.fetch, a.match, "FETCH_SIZE", a.last)
+    wv = counter_values(a.write, a.match, "WRITE_SIZE", a.last)
     print(f"copy of {a.copy_bytes} bytes: FETCH_SIZE {cf_mean:.6g} KiB -> factor {kf:.4f}; "
           f"WRITE_SIZE {cw_mean:.6g} KiB -> factor {kw:.4f}")
     print()
@@ -135,11 +165,20 @@ def cmd_traffic(a):
     wr = kw * 1024.0 * sw / nw
     print(f"| all | {nf} | {rd / 1e9:.3f} | {wr / 1e6:.2f} |")
     print()
-    kern = "k_filter32" if "k_filter32" in a.match else "k_filter"
+    kern = a.kernel or ("k_filter32" if "k_filter32" in a.match else "k_filter")
     rec = {"kernel": kern, "workload": a.workload, "sources_digest": sources_digest(kern),
            "launches": nf, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
            "bytes_per_launch": rd + wr, "fetch_factor": kf, "write_factor": kw}
     print("traffic-record: " + json.dumps(rec))
+
+
+def cmd_trace(a):
+    """Average duration of each matching kernel's dispatches in a trace."""
+    print("| kernel | dispatches | avg us | min us | max us |")
+    print("|---|---:|---:|---:|---:|")
+    for name, v in sorted(trace_durations(a.dir, a.match, a.last).items()):
+        print(f"| {_short(name)} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | "
+              f"{min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} |")
 
 
 def cmd_counters(a):
@@ -225,6 +264,11 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--match", default="k_filter<")
     t.add_argument("--workload", default="planted24k")
+    t.add_argument("--last", type=int, default=0,
+                   help="only each kernel's last N dispatches of the run (0: all)")
+    t.add_argument("--kernel", default="", choices=[""] + sorted(KERNEL_SOURCES),
+                   help="kernel whose sources the record's digest covers "
+                        "(default: k_filter32 or k_filter, from --match)")
     bw = sub.add_parser("bandwidth")
     for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
         bw.add_argument("--" + k.replace("_", "-"), required=True)
@@ -232,12 +276,17 @@ def main(argv=None):
     bw.add_argument("--match", default="",
                     help="comma-separated substrings of the kernels to list (all if empty)")
     bw.add_argument("--peak-gbs", type=float, default=8000.0)
+    tr = sub.add_parser("trace")
+    tr.add_argument("dir")
+    tr.add_argument("--match", default="k_filter<")
+    tr.add_argument("--last", type=int, default=0,
+                    help="only each kernel's last N dispatches of the run (0: all)")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--match", default="k_filter<")
     a = ap.parse_args(argv)
     {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters,
-     "bandwidth": cmd_bandwidth}[a.cmd](a)
+     "bandwidth": cmd_bandwidth, "trace": cmd_trace}[a.cmd](a)
 
 
 if __name__ == "__main__":

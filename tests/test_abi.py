@@ -165,3 +165,23 @@ def test_nex_linear_matches_oracle_and_rejects_bad_input():
     for bad in [(-1, 5, 0.0, 1.0, 0.5), (1, 5, 1.0, 1.0, 0.5), (1, 5, 0.0, float("nan"), 0.5)]:
         with pytest.raises(chase.ChaseError):
             chase.nex_linear(*bad)
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, 0, 0, 0, 0), "N must be"),
+    ((10, 9, 10, 0, 10), "ldh"),
+    ((10, 10, 10, -1, 5), "r0"),
+    ((10, 10, 10, 6, 5), "r0 + nrows"),
+    ((10, 10, 7, 0, 8), "ldr"),
+    ((200000, 200000, 200000, 0, 1), "N must be"),
+])
+def test_ingest_arguments_rejected_before_device_work(args, msg):
+    L = chase.lib()
+    N, ldh, ldr, r0, nrows = args
+    for fn in (L.chase_ingest_rows, L.chase_ingest_rows_host):
+        st = fn(ctypes.c_void_p(16), N, ldh, ctypes.c_void_p(16), ldr, r0, nrows, None)
+        assert st == chase.CHASE_EINVAL and msg in chase.last_error()
+    st = L.chase_hermitian_complete(ctypes.c_void_p(16), 10, 10, ord("X"), None)
+    assert st == chase.CHASE_EINVAL and "uplo" in chase.last_error()
+    st = L.chase_ingest_rows(None, 10, 10, ctypes.c_void_p(16), 10, 0, 3, None)
+    assert st == chase.CHASE_EINVAL and "NULL" in chase.last_error()

@@ -297,3 +297,40 @@ def test_eq_s2_endpoints_rounding_and_floor():
     assert steps.nex_linear(0, 1, 0.0, 2.0, 1.0) == 1          # 0.5 rounds up
     assert steps.nex_linear(10, 0, 0.0, 1.0, 3.0) == 0         # extrapolation floored at 0
     assert steps.nex_linear(10, 20, 0.0, 1.0, 1.5) == 25       # extrapolates above
+
+
+# ---------------------------------------------------------------- ingesting H
+
+def test_hermitian_from_triangle_is_fixed_by_its_invariants():
+    # Hermitian to the bit, the stored strict triangle kept, a real diagonal
+    # equal to the stored one's real part: these determine the result.
+    rng = np.random.default_rng(7)
+    N = 37
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    bits = lambda X: X.view(np.uint64)
+    for lower in (True, False):
+        C = steps.hermitian_from_triangle(A, lower)
+        assert np.array_equal(C, C.conj().T)
+        m = np.tril(np.ones((N, N), bool), -1) if lower else np.triu(np.ones((N, N), bool), 1)
+        assert np.array_equal(bits(C[m]), bits(A[m]))
+        assert np.array_equal(C.diagonal().real, A.diagonal().real)
+        assert np.all(C.diagonal().imag == 0.0)
+    # Lower and upper completions of the same data are each other's conjugates.
+    assert np.array_equal(steps.hermitian_from_triangle(A, True),
+                          np.conj(steps.hermitian_from_triangle(A.T, False)))
+
+
+def test_hermitian_from_triangle_special_cases():
+    # A Hermitian matrix is its own completion from either triangle.
+    H = synth.dk_matrix(50, seed=2)
+    assert np.array_equal(steps.hermitian_from_triangle(H, True), H)
+    assert np.array_equal(steps.hermitian_from_triangle(H, False), H)
+    # The oracle eigensolver reads only the lower triangle of its argument;
+    # LAPACK reading only the upper triangle of the completion must agree.
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60))
+    C = steps.hermitian_from_triangle(A, True)
+    w_lo = eig.eigh_lowest(A, 60)[0]
+    w_up = np.linalg.eigvalsh(C, UPLO="U")
+    assert np.allclose(w_lo, w_up, rtol=0, atol=1e-12 * np.abs(w_up).max())
+    assert steps.hermitian_from_triangle(np.array([[2 + 3j]]), True)[0, 0] == 2.0
