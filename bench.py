@@ -241,14 +241,40 @@ def cpu_baseline(w, seed, budget_s):
         Hs, _, _ = synth.planted_matrix(ns2, seed=seed, n_clusters=nc, cluster_size=10)
     else:
         Hs = synth.dk_matrix(ns2, seed=seed, std=w["std"], decay=w["decay"])
+    cores = eig.max_threads()
     t0 = time.perf_counter()
-    eig.eigh_lowest(Hs, min(w["nev"], ns2))
+    eig.eigh_lowest(Hs, min(w["nev"], ns2), nthreads=cores)
     t = time.perf_counter() - t0
     scaled = t * (N / ns2) ** 3
-    return {"value": scaled, "unit": "s", "cores": eig.max_threads(), "kind": "oracle",
-            "sample": f"oracle (Householder tridiagonalisation + implicit QR + "
-                      f"back-transform, FP64) on one N={ns2} matrix of the same "
-                      f"family took {t:.2f} s; scaled by (N/{ns2})^3 to N={N}"}
+    out = {"value": scaled, "unit": "s", "cores": cores, "kind": "oracle",
+           "sample": f"oracle (Householder tridiagonalisation + implicit QR + "
+                     f"back-transform, FP64) on one N={ns2} matrix of the same "
+                     f"family took {t:.2f} s; scaled by (N/{ns2})^3 to N={N}",
+           "host": host_description()}
+    if ns2 == N:
+        # The whole workload fits the budget: also on one core.
+        t0 = time.perf_counter()
+        eig.eigh_lowest(Hs, min(w["nev"], ns2), nthreads=1)
+        out["value_1core"] = time.perf_counter() - t0
+        eig.eigh_lowest(Hs[:2, :2], 1, nthreads=cores)     # restore the thread count
+    return out
+
+
+def host_description():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, the
+    process's affinity mask and OMP_NUM_THREADS."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS", "")}
 
 
 def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs=None):
