@@ -110,7 +110,7 @@ namespace {
 // workgroup's time falls as 1/splits.  Splitting costs a partial-sum pass
 // (2 * splits * N * n * 16 bytes), charged at 2% per split.
 FilterPlan plan_blocks(int64_t N, int wn, int cb) {
-    static const int occ[11] = {0, 3, 2, 2, 2, 2, 2, 1, 1, 1, 1};
+    static const int occ[11] = {0, 3, 2, 2, 2, 3, 2, 2, 2, 1, 1};
     FilterPlan p{};
     p.wn = wn;
     p.cb = cb;
