@@ -134,6 +134,91 @@ __global__ __launch_bounds__(1024) void k_chol_factor(Z *G, int n, double shift,
     if (t == 0) *info = 0;
 }
 
+// The same factor with the matrix held in LDS for orders up to
+// kCholLds: the packed lower triangle (entry (i, j), j <= i, at
+// i (i + 1) / 2 + j; 158 KB at n = 140), one column and the scale factors
+// fit gfx950's 160 KB, so no step waits on L2.  Same operations in the same
+// order as k_chol_factor; X = L^{-1} overwrites L in place (column k of L is
+// saved before row k of X takes its place), and the (row, column) loops run
+// on a 32 x 32 thread grid instead of dividing a flat index.
+constexpr int kCholLds = 140;
+
+__global__ __launch_bounds__(1024) void k_chol_factor_lds(const Z *G, int n, double shift,
+                                                          Z *B, int *info) {
+    __shared__ Z T[kCholLds * (kCholLds + 1) / 2];
+    __shared__ Z colk[kCholLds];
+    __shared__ double dsc[kCholLds];
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int tr = t >> 5, tc = t & 31;
+    auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
+    if (t == 0) bad = 0x7fffffff;
+    __syncthreads();
+    for (int j = t; j < n; j += nt) {
+        const double gjj = G[(int64_t)j * n + j].x;
+        if (!(gjj > 0.0) || !isfinite(gjj)) atomicMin(&bad, j + 1);   // LDS atomic
+        dsc[j] = gjj > 0.0 ? 1.0 / sqrt(gjj) : 0.0;
+    }
+    __syncthreads();
+    if (bad != 0x7fffffff) {
+        if (t == 0) *info = bad;
+        return;
+    }
+    for (int i = tr; i < n; i += 32)
+        for (int j = tc; j <= i; j += 32) {
+            Z v = zscale(G[(int64_t)i * n + j], dsc[i] * dsc[j]);
+            if (i == j) v = Z{v.x + shift, 0.0};
+            T[at(i, j)] = v;
+        }
+    __syncthreads();
+    // Right-looking Cholesky, lower.
+    for (int k = 0; k < n; ++k) {
+        const double piv = T[at(k, k)].x;
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (t == 0) *info = k + 1;
+            return;   // uniform: every thread read the same pivot
+        }
+        const double l = sqrt(piv), il = 1.0 / l;
+        __syncthreads();   // the pivot is read everywhere before it is replaced
+        for (int i = k + 1 + t; i < n; i += nt) {
+            const Z v = zscale(T[at(i, k)], il);
+            T[at(i, k)] = v;
+            colk[i] = v;
+        }
+        if (t == 0) T[at(k, k)] = Z{l, 0.0};
+        __syncthreads();
+        for (int i = k + 1 + tr; i < n; i += 32) {
+            const Z ci = colk[i];
+            for (int j = k + 1 + tc; j <= i; j += 32)
+                T[at(i, j)] = zsub(T[at(i, j)], zmul(ci, zconj(colk[j])));
+        }
+        __syncthreads();
+    }
+    // X = L^{-1} in place, right-looking: X[k][j] *= 1/L[k][k] (j <= k, with
+    // X[k][k] = 1 before), then X[i][j] -= L[i][k] X[k][j] for i > k
+    // (X[i][k] = 0 before).
+    for (int k = 0; k < n; ++k) {
+        for (int i = k + 1 + t; i < n; i += nt) colk[i] = T[at(i, k)];
+        const double xkk = 1.0 / T[at(k, k)].x;
+        __syncthreads();
+        for (int j = t; j <= k; j += nt)
+            T[at(k, j)] = zscale(j == k ? Z{1.0, 0.0} : T[at(k, j)], xkk);
+        __syncthreads();
+        for (int i = k + 1 + tr; i < n; i += 32) {
+            const Z ci = colk[i];
+            for (int j = tc; j <= k; j += 32) {
+                const Z cur = j == k ? Z{0.0, 0.0} : T[at(i, j)];
+                T[at(i, j)] = zsub(cur, zmul(ci, T[at(k, j)]));
+            }
+        }
+        __syncthreads();
+    }
+    for (int j = tr; j < n; j += 32)          // B row j, column i
+        for (int i = tc; i < n; i += 32)
+            B[(int64_t)j * n + i] = i >= j ? zscale(zconj(T[at(i, j)]), dsc[j]) : Z{0.0, 0.0};
+    if (t == 0) *info = 0;
+}
+
 // ---------------------------------------------------------- Jacobi
 // Round-robin pairing of m (even) indices, round r, pair k.
 __device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
@@ -329,6 +414,12 @@ inline int grid_for(int64_t total) {
 
 void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
                     hipStream_t s) {
+    if (n <= kCholLds) {
+        hipLaunchKernelGGL(k_chol_factor_lds, dim3(1), dim3(1024), 0, s, (const Z *)G, n, shift,
+                           B, info);
+        check_launch("k_chol_factor_lds");
+        return;
+    }
     hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, G, n, shift, B, work,
                        info);
     check_launch("k_chol_factor");

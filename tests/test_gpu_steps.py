@@ -133,7 +133,9 @@ def test_lanczos_vs_oracle():
                                                  (1200, 50, 17, False), (64, 64, 0, False),
                                                  (3000, 400, 100, False), (1100, 1024, 0, False),
                                                  (2000, 180, 0, True), (2000, 181, 0, False),
-                                                 (500, 2, 0, False), (500, 1, 0, False)])
+                                                 (500, 2, 0, False), (500, 1, 0, False),
+                                                 (1500, 140, 0, True), (1500, 141, 0, False),
+                                                 (900, 144, 5, False)])
 def test_qr_vs_oracle(N, n, nlocked, graded):
     torch_cuda()
     V = synth.random_block(N, n, seed=N + n)
@@ -151,6 +153,17 @@ def test_qr_vs_oracle(N, n, nlocked, graded):
     assert np.abs(got[:, nlocked:] - ref).max() <= 1e-13 * max(cond, 1.0) * np.sqrt(N)
     Qa = got
     assert np.abs(Qa.conj().T @ Qa - np.eye(n)).max() <= 1e-14 * np.sqrt(N)
+
+
+@pytest.mark.parametrize("n", [20, 140, 141, 300])
+def test_qr_breakdown_names_the_dependent_column(n):
+    # A zero column has a zero Gram diagonal: both factor kernels (the
+    # LDS-resident one up to 140 columns, the L2 one above) must report it.
+    torch_cuda()
+    V = synth.random_block(700, n, seed=n)
+    V[:, 7] = 0.0
+    with pytest.raises(chase.ChaseError, match="breakdown at column 7"):
+        chase.qr(dev_block(V), 0)
 
 
 def test_rayleigh_ritz_vs_oracle():
