@@ -631,8 +631,8 @@ def main():
                          "the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                                   "use --gpus 1 (multi-GPU sharding is a design note)"}))
+        print(json.dumps({"error": "the solver runs on one GPU only; use --gpus 1 "
+                                   "(row-sharding H over several GPUs is designed, not built)"}))
         sys.exit(2)
 
     import torch
