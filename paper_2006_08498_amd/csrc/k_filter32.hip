@@ -173,8 +173,11 @@ __global__ __launch_bounds__(256) void k_filter32_reduce(
     }
 }
 
+// Prefetch depth per tile width, measured on MI355X at N = 24000 and 60000:
+// width 7 needs the 6-deep ring (89-95 -> 114-124 TFLOP/s); widths 8-10 run
+// best at 4.
 constexpr int prefetch_depth32(int wn) {
-    return wn <= 4 ? 8 : wn <= 6 ? 6 : 4;
+    return wn <= 4 ? 8 : wn <= 7 ? 6 : 4;
 }
 
 template <int WN>
@@ -238,7 +241,7 @@ namespace {
 
 // As the FP64 plan, with the FP32 kernels' register budgets.
 FilterPlan plan32_blocks(int64_t N, int wn, int cb) {
-    static const int occ[11] = {0, 4, 3, 2, 2, 2, 1, 2, 1, 1, 1};
+    static const int occ[11] = {0, 4, 3, 2, 2, 2, 1, 1, 1, 1, 1};
     FilterPlan p{};
     p.wn = wn;
     p.cb = cb;
