@@ -282,3 +282,20 @@ def test_scalar_matrix():
     V = host(r.V)
     assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-12
     assert np.linalg.norm(H @ V - V * r.eigvals[None, :], axis=0).max() <= 1e-10 * 3.25
+
+
+@pytest.mark.parametrize("precision", [chase.CHASE_FP64, chase.CHASE_MIXED])
+def test_h_is_read_only_and_padding_is_ignored(precision):
+    """H with leading dimension N + 5 (NaN in the padding rows): the solve
+    reads only the N x N matrix and writes none of it."""
+    torch = torch_cuda()
+    N, ld = 700, 705
+    H = synth.dk_matrix(N, seed=4)
+    buf = torch.full((N, ld), complex("nan"), dtype=torch.complex128, device="cuda")
+    dH = buf.t()[:N, :]                                 # column-major, ldh = 705
+    dH.copy_(torch.from_numpy(H))
+    before = torch.view_as_real(buf).view(torch.int64).clone()
+    r = chase.solve(dH, 8, 6, precision=precision)
+    assert r.status == chase.CHASE_OK
+    assert torch.equal(torch.view_as_real(buf).view(torch.int64), before)
+    _check_against_oracle(H, r, 8)
