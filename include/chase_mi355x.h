@@ -312,6 +312,11 @@ int chase_lanczos_bounds(const double *h_alpha, const double *h_beta,
  * among themselves, so that span is kept: two classical Gram-Schmidt passes
  * against the locked columns, then shifted CholeskyQR3 with column
  * scaling.  The result equals Q of V_active = Q R with diag(R) > 0.
+ * Requires 1 <= n <= min(N, 1024), 0 <= nlocked <= n, ldv >= n.  A
+ * numerically rank-deficient active block (a Cholesky breakdown) returns
+ * CHASE_EINTERNAL with the dependent column named in chase_last_error();
+ * the block is then partly transformed.  (Inside a solve the column is
+ * replaced by a fresh random vector and the QR redone instead.)
  */
 int chase_qr(chase_z *dV, int64_t N, int64_t ldv, int32_t n,
              int32_t nlocked, void *stream);
