@@ -303,7 +303,9 @@ def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs
     infos = []
     t0 = time.perf_counter()
     for i in range(steps):
+        ts = time.perf_counter()
         r = chase.solve(H, nev, nex, w["tol"], w["degree_max"], workspace=ws, **opts)
+        r.info["wall_s"] = time.perf_counter() - ts     # the call returns when done
         infos.append(r.info)
         log(f"step {i}: {r.info['t_total']:.3f} s, {r.info['iterations']} it, "
             f"{r.info['matvecs_filter']} filter mat-vecs "
@@ -737,6 +739,9 @@ def main():
         "iterations": infos[-1]["iterations"],
         "matvecs_filter": infos[-1]["matvecs_filter"],
         "matvecs_filter_fp32": infos[-1]["matvecs_filter_fp32"],
+        "step_s": {"median": float(np.median([i["wall_s"] for i in infos])),
+                   "min": float(np.min([i["wall_s"] for i in infos])),
+                   "each": [i["wall_s"] for i in infos]},
         "phases_s": phases,
         "phase_roofline": phase_roof,
         "check": chk,
