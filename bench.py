@@ -165,6 +165,10 @@ def run_serve(args):
         "fused_ticks": peak["fused_ticks"], "fused_steps": peak["fused_steps"],
         "check": {"max_resid_rel_sampled": worst},
     }
+    out["roofline"] = serve_roofline(done, makespan)
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample")
+        out["cpu_baseline"] = serve_cpu_baseline(sched, cfg, args.cpu_budget)
     if args.serve_solo_baseline:
         # The same requests solved one after another, each alone on the GPU
         # with the plain FP64 path.
@@ -182,6 +186,43 @@ def run_serve(args):
         out["solo_fp64_sum_s"] = t_solo
         out["speedup_served_over_solo_fp64"] = t_solo / makespan
     print(json.dumps(out), flush=True)
+
+
+def serve_roofline(done, makespan):
+    """The dominant filter kernel (FP64 or FP32, by summed launch time) over
+    all served requests: its algorithmic flops (8 N^2 per column product)
+    over the whole makespan, a chip-level rate that counts idle time too,
+    and, beside it, the rate each launch saw while the slots shared the
+    GPU (flops over the summed launch durations)."""
+    f64 = sum(r.info["gemm_flops"] for _, r, _ in done)
+    t64 = sum(r.info["gemm_time"] for _, r, _ in done)
+    n64 = sum(r.info["gemm_launches"] for _, r, _ in done)
+    f32 = sum(8.0 * float(q["N"]) ** 2 * r.info["matvecs_filter_fp32"] for q, r, _ in done)
+    t32 = sum(r.info["t_filter32_kernels"] for _, r, _ in done)
+    n32 = sum(r.info["filter32_launches"] for _, r, _ in done)
+    if t32 > t64:
+        kern, fl, tk, nl, peak = "k_filter32 (FP32 MFMA)", f32, t32, n32, FP32_PEAK_TFLOPS
+    else:
+        kern, fl, tk, nl, peak = "k_filter (FP64 MFMA)", f64, t64, n64, FP64_PEAK_TFLOPS
+    ach = fl / makespan / 1e12 if makespan > 0 else 0.0
+    return {"bound": "mfma", "kernel": kern + ", every slot's launches",
+            "achieved": ach, "achieved_is": "algorithmic flops / makespan (chip level, "
+                                            "idle time included)",
+            "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+            "launches": nl, "per_launch_tflops_while_sharing": fl / tk / 1e12 if tk > 0 else 0.0}
+
+
+def serve_cpu_baseline(sched, cfg, budget_s):
+    """The oracle on a bounded sample of the largest request's family,
+    scaled by (N_r / N)^3 and summed over every request of the schedule."""
+    top = max(q["N"] for q in sched)
+    w = dict(kind="dk", N=top, nev=max(q["nev"] for q in sched), std=cfg["std"],
+             decay=cfg["decay"])
+    cb = cpu_baseline(w, 0, budget_s)
+    total = sum(cb["value"] * (q["N"] / top) ** 3 for q in sched)
+    return {"value": total, "unit": "s", "cores": cb["cores"], "kind": "oracle",
+            "sample": cb["sample"] + f"; summed over the {len(sched)} requests by "
+                                     f"(N_r/{top})^3", "host": cb["host"]}
 
 
 def log(msg):
