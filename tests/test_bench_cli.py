@@ -28,3 +28,56 @@ def test_serve_schedule_is_seeded_and_shaped():
     assert t[0] == 0.0 and all(x <= y for x, y in zip(t, t[1:]))
     # mean gap close to 1/4 s (Poisson at 4 per second)
     assert 0.15 < t[-1] / (len(t) - 1) < 0.35
+
+
+def _info(**kw):
+    base = dict(filter_flops=0.0, t_filter_kernels=0.0, filter_launches=0, t_filter=1.0,
+                matvecs_filter=0, matvecs_filter_fp32=0, t_filter32_kernels=0.0,
+                filter32_launches=0, gemm_time=0.0, gemm_flops=0.0, gemm_launches=0,
+                t_shadow=0.0, t_lanczos=0.1, t_qr=0.1, t_rr=0.1, t_resid=0.1, t_total=1.5,
+                lanczos_flops=1.0, lanczos_bytes=1.0, filter_bytes=1.0, qr_flops=1.0,
+                qr_bytes=1.0, rr_flops=1.0, rr_bytes=1.0, resid_flops=1.0, resid_bytes=1.0)
+    base.update(kw)
+    return base
+
+
+def test_kernel_roofline_reports_the_dominant_kernel_and_gates_traffic():
+    import bench
+    N = 24000
+    unit = 8.0 * N * N
+    # FP64 launches dominate: achieved = flops / summed launch time.
+    i64 = _info(gemm_time=2.0, gemm_flops=unit * 20000, gemm_launches=200,
+                matvecs_filter=20000, filter_flops=unit * 20000, t_filter_kernels=2.0)
+    S, roof, phase, phases, a64, a32 = bench.kernel_roofline([i64], N, "planted24k")
+    assert roof["kernel"].startswith("k_filter ") and roof["unit"] == "TFLOP/s"
+    assert abs(roof["achieved"] - unit * 20000 / 2.0 / 1e12) < 1e-9
+    assert abs(roof["frac"] - roof["achieved"] / bench.FP64_PEAK_TFLOPS) < 1e-12
+    assert roof["avg_launch_ms"] == 10.0
+    # The committed planted N = 24000 record matches the kernel sources, so
+    # its traffic is reported; an unprofiled workload reports none.
+    assert roof["traffic"] is not None and roof["traffic"] > 16.0 * N * N
+    assert bench.kernel_roofline([i64], N, "no-such-workload")[1]["traffic"] is None
+    # FP32 launches dominate.
+    i32 = _info(gemm_time=1.0, gemm_flops=unit * 100, gemm_launches=10,
+                matvecs_filter=30000, matvecs_filter_fp32=25000, t_filter32_kernels=3.0,
+                filter32_launches=300, filter_flops=unit * 30000, t_filter_kernels=1.0)
+    roof32 = bench.kernel_roofline([i32], N, "planted24k")[1]
+    assert roof32["kernel"].startswith("k_filter32") and roof32["peak"] == bench.FP32_PEAK_TFLOPS
+    assert abs(roof32["achieved"] - unit * 25000 / 3.0 / 1e12) < 1e-9
+    assert roof32["traffic"] is None          # no FP32 record for that workload
+
+
+def test_serve_roofline_is_flops_over_the_makespan():
+    import bench
+
+    class R:
+        def __init__(self, info):
+            self.info = info
+    info = dict(gemm_flops=4e15, gemm_time=100.0, gemm_launches=50, matvecs_filter_fp32=0,
+                t_filter32_kernels=0.0, filter32_launches=0)
+    done = [({"N": 8000}, R(info), 0.0), ({"N": 4000}, R(info), 0.0)]
+    roof = bench.serve_roofline(done, makespan=100.0)
+    assert roof["kernel"].startswith("k_filter ")
+    assert abs(roof["achieved"] - 8e15 / 100.0 / 1e12) < 1e-9
+    assert abs(roof["per_launch_tflops_while_sharing"] - 8e15 / 200.0 / 1e12) < 1e-9
+    assert roof["launches"] == 100
