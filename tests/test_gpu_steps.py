@@ -129,18 +129,20 @@ def test_lanczos_vs_oracle():
     assert got[2] >= lam[-1] and got[0] >= lam[0] - 1e-12
 
 
-@pytest.mark.parametrize("N,n,nlocked,graded", [(1000, 40, 0, False), (777, 33, 0, True),
-                                                 (1200, 50, 17, False), (64, 64, 0, False),
-                                                 (3000, 400, 100, False), (1100, 1024, 0, False),
-                                                 (2000, 180, 0, True), (2000, 181, 0, False),
-                                                 (500, 2, 0, False), (500, 1, 0, False),
-                                                 (1500, 140, 0, True), (1500, 141, 0, False),
-                                                 (900, 144, 5, False)])
+@pytest.mark.parametrize("N,n,nlocked,graded", [(1000, 40, 0, 0), (777, 33, 0, 8),
+                                                 (1200, 50, 17, 0), (64, 64, 0, 0),
+                                                 (3000, 400, 100, 0), (1100, 1024, 0, 0),
+                                                 (2000, 180, 0, 8), (2000, 181, 0, 0),
+                                                 (500, 2, 0, 0), (500, 1, 0, 0),
+                                                 (1500, 140, 0, 8), (1500, 141, 0, 0),
+                                                 (900, 144, 5, 0), (1000, 60, 0, 12),
+                                                 (1600, 200, 0, 12)])
 def test_qr_vs_oracle(N, n, nlocked, graded):
+    """graded: column norms fall from 1 to 10^-graded across the block."""
     torch_cuda()
     V = synth.random_block(N, n, seed=N + n)
     if graded:
-        V = V * np.logspace(0, -8, n)[None, :]
+        V = V * np.logspace(0, -graded, n)[None, :]
     if nlocked:
         V[:, :nlocked] = steps.qr_orth(V[:, :nlocked])
     dV = dev_block(V)
