@@ -274,8 +274,9 @@ def cpu_baseline(w, seed, budget_s):
     t0 = time.perf_counter()
     eig.eigh_lowest(Hs, min(w["nev"], ns))
     t_small = time.perf_counter() - t0
-    # Predict a sample that takes about budget_s and run it.
-    ns2 = int(ns * (budget_s / max(t_small, 1e-3)) ** (1.0 / 3.0))
+    # Predict a sample that takes about a third of budget_s and time it
+    # three times (the median is reported).
+    ns2 = int(ns * (budget_s / 3.0 / max(t_small, 1e-3)) ** (1.0 / 3.0))
     ns2 = max(ns, min(ns2, N))
     if w["kind"] == "planted":
         nc = max(1, min(20, ns2 // 100))
@@ -283,15 +284,19 @@ def cpu_baseline(w, seed, budget_s):
     else:
         Hs = synth.dk_matrix(ns2, seed=seed, std=w["std"], decay=w["decay"])
     cores = eig.max_threads()
-    t0 = time.perf_counter()
-    eig.eigh_lowest(Hs, min(w["nev"], ns2), nthreads=cores)
-    t = time.perf_counter() - t0
+    reps = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        eig.eigh_lowest(Hs, min(w["nev"], ns2), nthreads=cores)
+        reps.append(time.perf_counter() - t0)
+    t = float(np.median(reps))
     scaled = t * (N / ns2) ** 3
     out = {"value": scaled, "unit": "s", "cores": cores, "kind": "oracle",
            "sample": f"oracle (Householder tridiagonalisation + implicit QR + "
                      f"back-transform, FP64) on one N={ns2} matrix of the same "
-                     f"family took {t:.2f} s; scaled by (N/{ns2})^3 to N={N}",
-           "host": host_description()}
+                     f"family took {t:.2f} s (median of 3); scaled by (N/{ns2})^3 "
+                     f"to N={N}",
+           "repeats_s": reps, "host": host_description()}
     if ns2 == N:
         # The whole workload fits the budget: also on one core.
         t0 = time.perf_counter()
