@@ -7,7 +7,10 @@ already resident in HBM.  Prints one JSON line.
 Default workload: planted spectrum, N = 24000 complex128, H = Q diag(lam) Q^H
 with Q Haar (device QR of a Philox Gaussian matrix), lam = 20 clusters of 10
 eigenvalues 1e-4 apart in [2.0, 2.476] plus the rest uniform in [2.5, 8);
-nev = 100, nex = 40, degree <= 20, tol = 1e-10.
+nev = 100, nex = 40, degree <= 20, tol = 1e-10.  The same run then solves the
+largest single-GPU workload once in each form (sub-record "large": D + K,
+N = 100000, nev = 300, nex = 100, degree <= 30; mixed precision, then plain
+FP64 while the run is under 300 s), unless --large 0.
 """
 from __future__ import annotations
 
@@ -291,11 +294,34 @@ def cpu_baseline(w, seed, budget_s):
         reps.append(time.perf_counter() - t0)
     t = float(np.median(reps))
     scaled = t * (N / ns2) ** 3
+    # Fit points: the same family at N_s/4 and N_s/2 (median of 3 each) next
+    # to N_s, and the exponent of t ~ N^b through them (least squares in
+    # logs), to show how well the O(N^3) model holds at the sampled sizes.
+    pts = []
+    for frac in (4, 2):
+        nf = max(64, ns2 // frac)
+        if w["kind"] == "planted":
+            Hf, _, _ = synth.planted_matrix(nf, seed=seed, n_clusters=max(1, min(20, nf // 100)),
+                                            cluster_size=10)
+        else:
+            Hf = synth.dk_matrix(nf, seed=seed, std=w["std"], decay=w["decay"])
+        tf = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            eig.eigh_lowest(Hf, min(w["nev"], nf), nthreads=cores)
+            tf.append(time.perf_counter() - t0)
+        pts.append([nf, float(np.median(tf))])
+    pts.append([ns2, t])
+    b = float(np.polyfit(np.log([p[0] for p in pts]), np.log([p[1] for p in pts]), 1)[0])
     out = {"value": scaled, "unit": "s", "cores": cores, "kind": "oracle",
+           "extrapolated": ns2 < N,
            "sample": f"oracle (Householder tridiagonalisation + implicit QR + "
                      f"back-transform, FP64) on one N={ns2} matrix of the same "
-                     f"family took {t:.2f} s (median of 3); scaled by (N/{ns2})^3 "
-                     f"to N={N}",
+                     f"family took {t:.2f} s (median of 3); "
+                     + (f"extrapolated by (N/{ns2})^3 to N={N}, not measured"
+                        if ns2 < N else "the whole workload"),
+           "fit_points_n_s": pts, "fit_exponent": b,
+           "value_at_fit_exponent": t * (N / ns2) ** b,
            "repeats_s": reps, "host": host_description()}
     if ns2 == N:
         # The whole workload fits the budget: also on one core.
@@ -323,7 +349,8 @@ def host_description():
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS", "")}
 
 
-def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs=None):
+def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs=None,
+               degree_extra=None):
     """warmup untimed solves, then `steps` timed solves (the library call is
     synchronous); returns the info records, seconds per solve, last result."""
     import torch
@@ -334,6 +361,8 @@ def run_solves(H, w, ws, precision, steps, warmup, seed, switch_tol=None, graphs
         opts["switch_tol"] = switch_tol
     if graphs is not None:
         opts["graphs"] = graphs
+    if degree_extra is not None:
+        opts["degree_extra"] = degree_extra
     if N >= 50000:
         # Long solves report each iteration as it ends.
         def progress(info):
@@ -429,6 +458,58 @@ def kernel_roofline(infos, N, workload):
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, " \
                                "copy-calibrated)"
     return S, roof, phase_roof, phases, ach64, ach32
+
+
+def run_large(t_begin, fp64_deadline_s):
+    """The N = 100000 D + K workload (160 GB of H, generated on the device):
+    one mixed-precision solve, then, if the run is still inside the time
+    budget, one plain FP64 solve of the same matrix; each with the residual
+    and orthogonality checks, phase times and the dominant kernel's
+    roofline."""
+    import torch
+    from paper_2006_08498_amd import chase
+    name = "dk100k"
+    w = WORKLOADS[name]
+    N, nev, nex = w["N"], w["nev"], w["nex"]
+    rec = {"workload": f"{name}: dk N={N} nev={nev} nex={nex} degree<={w['degree_max']} "
+                       f"tol={w['tol']} std={w['std']} decay={w['decay']}",
+           "N": N, "nev": nev, "nex": nex, "degree_max": w["degree_max"], "tol": w["tol"],
+           "steps": 1, "warmup": 0}
+    log(f"large: generating {name} N={N} on the device")
+    t0 = time.perf_counter()
+    H, _ = make_matrix(w, 0)
+    torch.cuda.synchronize()
+    rec["generate_s"] = time.perf_counter() - t0
+    eig = {}
+    for prec in ("mixed", "fp64"):
+        if prec == "fp64" and time.perf_counter() - t_begin > fp64_deadline_s:
+            rec[prec] = {"skipped": f"past {fp64_deadline_s:.0f} s of the run"}
+            log("large: plain FP64 solve skipped (time budget)")
+            continue
+        precision = chase.CHASE_MIXED if prec == "mixed" else chase.CHASE_FP64
+        o = chase.default_opts(precision=precision)
+        ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8,
+                         device="cuda")
+        log(f"large: {prec} solve")
+        infos, per, r = run_solves(H, w, ws, precision, 1, 0, 0)
+        chk = check_result(H, r, None, w["tol"])
+        S, roof, phase_roof, phases, ach64, ach32 = kernel_roofline(infos, N, name)
+        rec[prec] = {"value": per, "unit": "s", "iterations": infos[-1]["iterations"],
+                     "matvecs_filter": infos[-1]["matvecs_filter"],
+                     "matvecs_filter_fp32": infos[-1]["matvecs_filter_fp32"],
+                     "filter_kernel_tflops_fp64": ach64, "filter_kernel_tflops_fp32": ach32,
+                     "phases_s": phases, "phase_roofline": phase_roof, "roofline": roof,
+                     "check": chk}
+        eig[prec] = r.eigvals
+        log(f"large: {prec} {per:.1f} s, check {chk}")
+        del ws, r
+        torch.cuda.empty_cache()
+    if "fp64" in eig:
+        rec["speedup_mixed_over_fp64"] = rec["fp64"]["value"] / rec["mixed"]["value"]
+        rec["max_eig_diff_mixed_vs_fp64"] = float(np.max(np.abs(eig["fp64"] - eig["mixed"])))
+    del H
+    torch.cuda.empty_cache()
+    return rec
 
 
 INGEST = dict(N=24000, std=0.02, decay=200.0)
@@ -633,6 +714,17 @@ def run_sequence(args):
         "check": chk,
         "roofline": roof,
     }
+    if args.large if args.large is not None else args.workload == "planted24k":
+        # The largest single-GPU workload timed in the same run: H of the
+        # default workload is released first (the large one needs 160 GB
+        # plus an 80 GB FP32 copy in mixed precision).
+        H = ws = r = r64 = None   # noqa: F841 - drop the references
+        torch.cuda.empty_cache()
+        try:
+            out["large"] = run_large(t_begin, fp64_deadline_s=300.0)
+        except Exception as e:   # noqa: BLE001 - recorded, the headline stands
+            log(f"large: failed: {e}")
+            out["large"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.seed, args.cpu_budget)
@@ -674,10 +766,18 @@ def main():
                          "library default if omitted")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="mixed workloads: skip timing the plain FP64 solve")
+    ap.add_argument("--degree-extra", type=int, default=None,
+                    help="filter steps added to each computed degree (library default if "
+                         "omitted)")
+    ap.add_argument("--large", type=int, choices=(0, 1), default=None,
+                    help="planted24k: also solve the N=100000 D+K workload once in mixed "
+                         "precision and once in plain FP64 (sub-record 'large'); on by "
+                         "default for planted24k")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): "
                          "the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
+    t_begin = time.perf_counter()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU only; use --gpus 1 "
                                    "(row-sharding H over several GPUs is designed, not built)"}))
@@ -733,7 +833,7 @@ def main():
     o = chase.default_opts(precision=precision)
     ws = torch.empty(chase.workspace_bytes(N, nev, nex, o), dtype=torch.uint8, device="cuda")
     infos, per, r = run_solves(H, w, ws, precision, args.steps, args.warmup, args.seed,
-                               args.switch_tol, args.graphs)
+                               args.switch_tol, args.graphs, args.degree_extra)
     chk = check_result(H, r, lam, w["tol"])
     log(f"check: {chk}")
     per_seed = None
@@ -749,7 +849,7 @@ def main():
             H, lam_s = make_matrix(w, sd)
             torch.cuda.synchronize()
             inf_s, per_s, r_s = run_solves(H, w, ws, precision, args.steps, args.warmup, sd,
-                                           args.switch_tol, args.graphs)
+                                           args.switch_tol, args.graphs, args.degree_extra)
             per_seed.append({"seed": sd, "value": per_s, "iterations": r_s.info["iterations"],
                              "check": check_result(H, r_s, lam_s, w["tol"])})
             log(f"seed {sd}: {per_s:.4f} s per solve")
@@ -803,7 +903,8 @@ def main():
         ws = torch.empty(chase.workspace_bytes(N, nev, nex, o64), dtype=torch.uint8,
                          device="cuda")
         infos64, per64, r64 = run_solves(H, w, ws, chase.CHASE_FP64, max(1, args.steps // 2),
-                                         min(args.warmup, 1), args.seed)
+                                         min(args.warmup, 1), args.seed,
+                                         degree_extra=args.degree_extra)
         chk64 = check_result(H, r64, lam, w["tol"])
         out["fp64_reference"] = {
             "value": per64, "unit": "s", "check": chk64,
@@ -811,6 +912,17 @@ def main():
             "matvecs_filter": infos64[-1]["matvecs_filter"],
             "max_eig_diff_vs_mixed": float(np.max(np.abs(r64.eigvals - r.eigvals))),
             "speedup_mixed_over_fp64": per64 / per}
+    if args.large if args.large is not None else args.workload == "planted24k":
+        # The largest single-GPU workload timed in the same run: H of the
+        # default workload is released first (the large one needs 160 GB
+        # plus an 80 GB FP32 copy in mixed precision).
+        H = ws = r = r64 = None   # noqa: F841 - drop the references
+        torch.cuda.empty_cache()
+        try:
+            out["large"] = run_large(t_begin, fp64_deadline_s=300.0)
+        except Exception as e:   # noqa: BLE001 - recorded, the headline stands
+            log(f"large: failed: {e}")
+            out["large"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.seed, args.cpu_budget)

@@ -188,8 +188,10 @@ const char *chase_last_error(void);
  * positive.  Requires 1 <= nev, 0 <= nex, nev + nex <= N, tol > 0,
  * nev + nex <= 1024 (with nex = 0 and nev < N one extra search vector is
  * carried internally: without it the top wanted vector cannot converge),
- * 2 <= degree_max <= 64 (degrees are even; an odd degree_max acts as
- * degree_max - 1).  Allocates its own workspace; runs on the null stream.
+ * 1 <= degree_max <= 64 (degrees are even, so an odd degree_max above 1
+ * acts as degree_max - 1; degree_max = 1 filters every vector with exactly
+ * one step per iteration).  Allocates its own workspace; runs on the null
+ * stream.
  */
 int chase_solve(const chase_z *dH, int64_t N, int32_t nev, int32_t nex,
                 double tol, int32_t degree_max,
@@ -278,8 +280,8 @@ int chase_shadow_c(const chase_z *dH, int64_t N, int64_t ldh, chase_c *dHc,
  * The whole Chebyshev filter with per-vector degrees on an N x n block,
  * in place: column j becomes C_m(L) v_j / C_m(t0), m = h_degrees[j],
  * L = (H - cI)/e, t0 = (mu1 - c)/e, c = (alpha+beta)/2, e = (beta-alpha)/2.
- * h_degrees: n even integers >= 2, ascending.  Returns the number of
- * column products in *matvecs (may be NULL).
+ * h_degrees: n integers, ascending, each 1 or even in [2, 64].  Returns the
+ * number of column products in *matvecs (may be NULL).
  */
 int chase_filter(const chase_z *dH, int64_t N, int64_t ldh,
                  chase_z *dV, int64_t ldv, int32_t n,
@@ -342,6 +344,12 @@ int chase_residuals(const chase_z *dH, int64_t N, int64_t ldh,
  * Dense Hermitian eigensolver for the reduced problem (on the device,
  * cyclic Jacobi): dG n x n row-major (leading dimension n), not modified;
  * h_w: n eigenvalues ascending; dY: n x n row-major eigenvectors (columns).
+ * 1 <= n <= 1024.  Sweeps run until the off-diagonal norm is below
+ * 1e-15 of the whole or stops falling below 1e-12 of it (the rounding
+ * floor); if neither happens within 30 sweeps (environment variable
+ * CHASE_JACOBI_MAX_SWEEPS overrides the cap, for diagnostics) the call
+ * returns CHASE_EINTERNAL, and so does a solve whose Rayleigh-Ritz phase
+ * meets that.  Scratch (4 n^2 complex) is allocated per call.
  */
 int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
                 void *stream);
@@ -351,7 +359,7 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
  * h_theta[j] and residual h_resid[j], the smallest m with
  * rho_j^m >= resid_j / tol_abs (rho_j of the supplement's Eq. S1 on the
  * interval [alpha, beta]) plus extra, clamped to [2, degree_max] and made
- * even; 2 for converged vectors.
+ * even; 2 for converged vectors; 1 for every vector when degree_max is 1.
  */
 int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
                   double tol_abs, double alpha, double beta,
@@ -458,9 +466,14 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots,
 
 /* Queues a request.  H is a host matrix (copied now, uploaded at admission,
  * counted in the footprint) when is_device == 0, else a caller-owned device
- * matrix with ldh == N that must stay valid until the request is polled
- * (not counted).  Options as for chase_solve_ex (no warm start).  Returns
- * CHASE_ENOMEM if the footprint alone exceeds the budget. */
+ * matrix with ldh == N that must stay valid and unmodified until the
+ * request is polled (not counted).  The server reads a device H on a
+ * stream of its own that is not ordered after the caller's streams: the
+ * work that writes H must have completed before this call (synchronise the
+ * stream that produced it).  Arguments and options are checked as by
+ * chase_solve_ex (no warm start; out_cols 0 or nev) before the request is
+ * queued: CHASE_EINVAL on a bad one.  Returns CHASE_ENOMEM if the footprint
+ * alone exceeds the budget. */
 int chase_server_submit(chase_server *srv, const chase_z *H, int is_device,
                         int64_t N, int64_t ldh, int32_t nev, int32_t nex,
                         double tol, int32_t degree_max, const chase_opts *o,
@@ -478,7 +491,12 @@ int chase_server_submit_fill(chase_server *srv, chase_fill_fn fill, void *user,
  * if not NULL, eigenvectors column-major into dV with ldv >= N, info if not
  * NULL, and if h_times3 is not NULL: seconds queued, seconds on the GPU,
  * latency from submission to completion), releases the request and returns
- * its status (CHASE_OK, CHASE_ENOCONV or the error). */
+ * its status (CHASE_OK, CHASE_ENOCONV or the error).  The eigenvectors are
+ * copied on a stream of the server's own, complete when the call returns;
+ * that copy is not ordered after the caller's streams, so no queued work
+ * may still use dV.  One poll collects a result: a concurrent poll of the
+ * same ticket gets CHASE_EINVAL (so does a NULL dV or ldv < N, after which
+ * the result can still be collected). */
 int chase_server_poll(chase_server *srv, uint64_t ticket, double *h_eigvals,
                       double *h_resid, chase_z *dV, int64_t ldv,
                       chase_info *info, double *h_times3);

@@ -182,8 +182,12 @@ def lanczos_bounds(al, be, N, ne):
 # --------------------------------------------------------------------------
 
 def degree_cap(degree_max):
-    """Largest even degree not above degree_max (degrees are even so that
-    every column of a two-buffer recurrence ends in the same buffer)."""
+    """Largest degree a vector may get: the largest even degree not above
+    degree_max (degrees are even so that every column of a two-buffer
+    recurrence ends in the same buffer), except that degree_max = 1 allows
+    exactly one step per iteration."""
+    if degree_max == 1:
+        return 1
     return max(2, degree_max - degree_max % 2)
 
 
@@ -191,8 +195,11 @@ def degree(res, tol_abs, lam, c, e, degree_max, extra=2):
     """Filter degree for one vector: the number of steps after which a
     residual res shrinking by 1/rho per step reaches tol_abs,
     m = ceil(ln(res / tol_abs) / ln rho) + extra, clamped to
-    [2, degree_cap] and rounded up to even."""
+    [2, degree_cap] and rounded up to even.  With degree_max = 1 every
+    vector gets one step."""
     cap = degree_cap(degree_max)
+    if cap == 1:
+        return 1
     if res <= tol_abs:
         return 2
     r = rho(lam, c, e)

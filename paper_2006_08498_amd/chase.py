@@ -583,6 +583,9 @@ class Server:
         N = H.shape[0]
         o = default_opts(**opt_kw)
         t = ctypes.c_uint64(0)
+        # The server reads H on a stream of its own, not ordered after the
+        # caller's: the work that produced H must be complete first.
+        _torch().cuda.current_stream(H.device).synchronize()
         st = lib().chase_server_submit(self._s, hp, 1, N, ldh, nev, nex, tol, degree_max,
                                        ctypes.byref(o), ctypes.byref(t))
         if st != CHASE_OK:
@@ -620,6 +623,9 @@ class Server:
         rs = np.zeros(nev)
         info = ChaseInfo()
         times = np.zeros(3)
+        # The result is copied on the server's own stream: work still queued
+        # on this stream may use the memory the allocator just handed out.
+        torch.cuda.current_stream(out.device).synchronize()
         st = lib().chase_server_poll(self._s, ticket, ev.ctypes.data_as(_P),
                                      rs.ctypes.data_as(_P), _dptr(out), N,
                                      ctypes.byref(info), times.ctypes.data_as(_P))

@@ -73,6 +73,10 @@ struct DevBuf {
 
 hipStream_t S(void *stream) { return reinterpret_cast<hipStream_t>(stream); }
 
+}  // namespace
+
+namespace chase {
+
 void validate_sizes(int64_t N, int32_t nev, int32_t nex) {
     REQUIRE(N >= 1, "N must be >= 1");
     REQUIRE(N <= (int64_t)1 << 31, "N too large for 32-bit row indices");
@@ -80,13 +84,6 @@ void validate_sizes(int64_t N, int32_t nev, int32_t nex) {
     REQUIRE(nex >= 0, "nex must be >= 0");
     REQUIRE((int64_t)nev + nex <= N, "nev + nex must be <= N");
     REQUIRE(nev + nex <= 1024, "nev + nex must be <= 1024");
-}
-
-chase_opts resolve(const chase_opts *o) {
-    chase_opts r;
-    chase_default_opts(&r);
-    if (o) r = *o;
-    return r;
 }
 
 void validate_opts(const chase_opts &o) {
@@ -99,6 +96,28 @@ void validate_opts(const chase_opts &o) {
     REQUIRE(o.lanczos_runs >= 1 && o.lanczos_runs <= 64, "lanczos_runs must be in [1, 64]");
     REQUIRE(o.switch_tol > 0.0, "switch_tol must be > 0");
     REQUIRE(o.graphs == 0 || o.graphs == 1, "graphs must be 0 or 1");
+}
+
+void validate_problem(int64_t N, int32_t nev, int32_t nex, double tol, int32_t degree_max,
+                      const chase_opts &o) {
+    validate_sizes(N, nev, nex);
+    REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be finite and > 0");
+    REQUIRE(degree_max >= 1 && degree_max <= 64, "degree_max must be in [1, 64]");
+    validate_opts(o);
+    REQUIRE(o.v0_cols >= 0 && o.v0_cols <= nev + nex, "v0_cols must be in [0, nev + nex]");
+    REQUIRE(o.out_cols == 0 || (o.out_cols >= nev && o.out_cols <= nev + nex),
+            "out_cols must be 0 or in [nev, nev + nex]");
+}
+
+}  // namespace chase
+
+namespace {
+
+chase_opts resolve(const chase_opts *o) {
+    chase_opts r;
+    chase_default_opts(&r);
+    if (o) r = *o;
+    return r;
 }
 
 }  // namespace
@@ -136,20 +155,13 @@ int chase_solve_ex(const chase_z *dH, int64_t N, int64_t ldh, int32_t nev,
                    int64_t ldv, void *dwork, size_t work_bytes, void *stream,
                    const chase_opts *o, chase_info *info) {
     return guarded([&]() -> int {
-        validate_sizes(N, nev, nex);
+        const chase_opts opts = resolve(o);
+        validate_problem(N, nev, nex, tol, degree_max, opts);
         REQUIRE(dH != nullptr, "dH is NULL");
         REQUIRE(ldh >= N, "ldh must be >= N");
-        REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be > 0");
-        REQUIRE(degree_max >= 2 && degree_max <= 64, "degree_max must be in [2, 64]");
         REQUIRE(h_eigvals != nullptr, "h_eigvals is NULL");
         REQUIRE(dV != nullptr, "dV is NULL");
         REQUIRE(ldv >= N, "ldv must be >= N");
-        const chase_opts opts = resolve(o);
-        validate_opts(opts);
-        REQUIRE(opts.v0_cols >= 0 && opts.v0_cols <= nev + nex,
-                "v0_cols must be in [0, nev + nex]");
-        REQUIRE(opts.out_cols == 0 || (opts.out_cols >= nev && opts.out_cols <= nev + nex),
-                "out_cols must be 0 or in [nev, nev + nex]");
         const Layout lay = make_layout(N, nev, nex, opts);
         hipStream_t s = S(stream);
         DevBuf own(dwork ? 0 : lay.total, s);
@@ -288,8 +300,9 @@ int chase_filter(const chase_z *dH, int64_t N, int64_t ldh, chase_z *dV,
         REQUIRE(beta > alpha && mu1 < alpha, "need mu1 < alpha < beta");
         int64_t mv = 0;
         for (int j = 0; j < n; ++j) {
-            REQUIRE(h_degrees[j] >= 2 && h_degrees[j] % 2 == 0 && h_degrees[j] <= 64,
-                    "degrees must be even, in [2, 64]");
+            REQUIRE(h_degrees[j] == 1 ||
+                        (h_degrees[j] >= 2 && h_degrees[j] % 2 == 0 && h_degrees[j] <= 64),
+                    "degrees must be 1 or even, in [2, 64]");
             REQUIRE(j == 0 || h_degrees[j] >= h_degrees[j - 1], "degrees must be ascending");
             mv += h_degrees[j];
         }
@@ -564,7 +577,7 @@ int chase_degrees(const double *h_theta, const double *h_resid, int32_t n,
     return guarded([&]() -> int {
         REQUIRE(n >= 0 && (n == 0 || (h_theta && h_resid && h_degrees)), "bad arguments");
         REQUIRE(beta > alpha, "need alpha < beta");
-        REQUIRE(tol_abs > 0.0 && degree_max >= 2 && extra >= 0, "bad tol/degree");
+        REQUIRE(tol_abs > 0.0 && degree_max >= 1 && extra >= 0, "bad tol/degree");
         const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
         for (int j = 0; j < n; ++j)
             h_degrees[j] = degree_for(h_resid[j], tol_abs, h_theta[j], c, e, degree_max, extra);

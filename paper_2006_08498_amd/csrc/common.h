@@ -180,7 +180,6 @@ struct JacobiGraphs {
     ~JacobiGraphs();
 };
 size_t jacobi_work_elems(int n);
-size_t jacobi_work_elems(int n);
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
                 hipStream_t s, JacobiGraphs *graphs = nullptr);
 // Symmetrise: G <- (G + G^H)/2, real diagonal.

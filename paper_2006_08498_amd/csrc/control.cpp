@@ -107,11 +107,16 @@ double rate(double lam, double c, double e) {
     return a + std::sqrt(a * a - 1.0);
 }
 
-int degree_cap(int degree_max) { return std::max(2, degree_max - degree_max % 2); }
+// Even degrees leave every column of the two-buffer recurrence in the same
+// buffer; degree_max = 1 is the one exception (one step for every vector).
+int degree_cap(int degree_max) {
+    return degree_max == 1 ? 1 : std::max(2, degree_max - degree_max % 2);
+}
 
 int degree_for(double res, double tol_abs, double lam, double c, double e,
                int degree_max, int extra) {
     const int cap = degree_cap(degree_max);
+    if (cap == 1) return 1;
     if (res <= tol_abs) return 2;
     const double r = rate(lam, c, e);
     if (!(r > 1.0 + 1e-12)) return cap;

@@ -20,9 +20,12 @@ Bounds lanczos_bounds(const double *al, const double *be, int k, int r,
 // with centre c and half-width e (1 inside the interval).
 double rate(double lam, double c, double e);
 
+// Largest degree: degree_max rounded down to even (at least 2), or 1 when
+// degree_max is 1.
 int degree_cap(int degree_max);
 
-// Smallest even m >= 2 (plus extra) with rate^m >= res / tol_abs, capped.
+// Smallest even m >= 2 (plus extra) with rate^m >= res / tol_abs, capped;
+// always 1 when degree_max is 1.
 int degree_for(double res, double tol_abs, double lam, double c, double e,
                int degree_max, int extra);
 

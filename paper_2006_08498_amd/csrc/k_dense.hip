@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 namespace chase {
@@ -539,7 +541,16 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
         const hipGraphExec_t *ex =
             graphs ? sweep_graphs(*graphs, A, A2, V, V2, n, m, grid, dnorm, work) : nullptr;
         double prev = 1e300;
-        for (int sweep = 0; sweep < 30; ++sweep) {
+        // Cyclic Jacobi converges quadratically (a few sweeps to the rounding
+        // floor at these orders); a diagnostic override of the cap lets the
+        // failure path be exercised.
+        int max_sweeps = 30;
+        if (const char *e = std::getenv("CHASE_JACOBI_MAX_SWEEPS")) {
+            const int v = std::atoi(e);
+            if (v >= 1) max_sweeps = v;
+        }
+        bool converged = false;
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
             // m - 1 (odd) rounds: each sweep leaves the result in the other
             // buffer of the pair, so consecutive sweeps alternate parity.
             if (ex) {
@@ -554,14 +565,20 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
             CHASE_HIP(hipStreamSynchronize(s));
             const double off = std::sqrt(hwork[0]), tot = std::sqrt(hwork[1]);
             if (!std::isfinite(off)) throw Error(5, "jacobi: non-finite matrix");
-            if (off <= 1e-15 * tot) break;
-            if (off <= 1e-12 * tot && off >= 0.5 * prev) break;   // rounding floor
+            if (off <= 1e-15 * tot || (off <= 1e-12 * tot && off >= 0.5 * prev)) {
+                converged = true;   // tiny, or at the rounding floor
+                break;
+            }
             prev = off;
         }
+        if (!converged)
+            throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
+                               std::to_string(max_sweeps) + " sweeps");
     }
     hipLaunchKernelGGL(k_sort_eig, dim3((n + 255) / 256), dim3(256), 0, s, A, V,
                        n, w, Y);
     check_launch("k_sort_eig");
 }
+
 
 }  // namespace chase

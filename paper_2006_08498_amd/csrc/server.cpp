@@ -53,6 +53,7 @@ struct Request {
     chase_info info{};
     void *dV = nullptr;     // N x nev column-major
     int slot = -1;
+    bool collecting = false;   // a poll is copying the result out
 };
 
 // Cross-request filter fusion.  Each running solve hands the FP64 filter
@@ -366,13 +367,11 @@ int srv_fail(int st, const std::string &m) {
 
 int submit_common(chase_server *s, std::unique_ptr<Request> r, uint64_t *ticket) {
     if (!s || !ticket) return srv_fail(CHASE_EINVAL, "NULL server or ticket");
-    if (r->N < 1 || r->nev < 1 || r->nex < 0 || (int64_t)r->nev + r->nex > r->N ||
-        r->nev + r->nex > 1024)
-        return srv_fail(CHASE_EINVAL, "bad N / nev / nex");
-    if (!(r->tol > 0.0) || r->degree_max < 2 || r->degree_max > 64)
-        return srv_fail(CHASE_EINVAL, "bad tol / degree_max");
-    if (r->opts.precision != CHASE_FP64 && r->opts.precision != CHASE_MIXED)
-        return srv_fail(CHASE_EINVAL, "unknown precision");
+    try {
+        validate_problem(r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts);
+    } catch (const Error &e) {
+        return srv_fail(e.status, e.what());
+    }
     if (r->opts.dV0 || r->opts.v0_cols != 0)
         return srv_fail(CHASE_EINVAL, "warm start is not supported by the server");
     if (r->opts.out_cols != 0 && r->opts.out_cols != r->nev)
@@ -482,16 +481,20 @@ int chase_server_poll(chase_server *s, uint64_t ticket, double *h_eigvals,
     if (!s) return srv_fail(CHASE_EINVAL, "NULL server");
     Request *r = nullptr;
     {
+        // Claim the result under the lock: a second poll of the same ticket
+        // while this one copies it out sees it claimed and is refused.
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->reqs.find(ticket);
         if (it == s->reqs.end()) return srv_fail(CHASE_EINVAL, "unknown ticket");
         r = it->second.get();
         if (r->state != St::Done) return CHASE_PENDING;
+        if (r->collecting) return srv_fail(CHASE_EINVAL, "the result is being collected");
+        if (r->dV && (!dV || ldv < r->N)) return srv_fail(CHASE_EINVAL, "dV is NULL or ldv < N");
+        r->collecting = true;
     }
     int st = r->status;
     try {
         if (r->dV) {
-            if (!dV || ldv < r->N) return srv_fail(CHASE_EINVAL, "dV is NULL or ldv < N");
             std::lock_guard<std::mutex> lk(s->copy_mu);
             CHASE_HIP(hipMemcpy2DAsync(dV, (size_t)ldv * sizeof(Z), r->dV,
                                        (size_t)r->N * sizeof(Z), (size_t)r->N * sizeof(Z),
@@ -508,6 +511,8 @@ int chase_server_poll(chase_server *s, uint64_t ticket, double *h_eigvals,
             h_times3[2] = secs(r->t_end - r->t_submit);     // latency
         }
     } catch (const Error &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->collecting = false;   // the result stays; the caller may poll again
         return srv_fail(e.status, e.what());
     }
     std::lock_guard<std::mutex> lk(s->mu);

@@ -87,10 +87,12 @@ Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o) {
 }
 
 // ------------------------------------------------------------ Filter
-// Columns sorted by ascending even degree; column j stops after deg[j]
-// steps, so step s runs on the suffix of columns with deg >= s.  Two
+// Columns sorted by ascending degree (1 or even); column j stops after
+// deg[j] steps, so step s runs on the suffix of columns with deg >= s.  Two
 // buffers: V holds Y_0 and every even iterate, B1 every odd iterate, each
-// step writing over the older iterate in place.
+// step writing over the older iterate in place.  Even-degree columns end in
+// V; the leading degree-1 columns end in B1 and are copied back
+// (finish_degree_one).
 std::vector<FilterCall> filter_steps(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1,
                                      int64_t ld, int n, const int *deg, double mu1,
                                      double alpha, double beta, Z *fpart) {
@@ -122,6 +124,17 @@ std::vector<FilterCall> filter_steps(const Z *H, int64_t ldh, int64_t N, Z *V, Z
     return out;
 }
 
+static int degree_one_count(const int *deg, int n) {
+    int n1 = 0;
+    while (n1 < n && deg[n1] == 1) ++n1;
+    return n1;
+}
+
+void finish_degree_one(Z *V, const Z *B1, int64_t ld, int64_t N, int n, const int *deg,
+                       hipStream_t s) {
+    copy_block(B1, ld, V, ld, N, degree_one_count(deg, n), s);
+}
+
 void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
                   int n, const int *deg, double mu1, double alpha, double beta,
                   Z *fpart, hipStream_t s, std::vector<hipEvent_t> *prof) {
@@ -143,10 +156,12 @@ void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
             prof->push_back(e2);
         }
     }
+    finish_degree_one(V, B1, ld, N, n, deg, s);
 }
 
 // Same recurrence on complex64 blocks with the complex64 shadow of H: the
-// coefficients are formed in FP64 and rounded once to FP32.
+// coefficients are formed in FP64 and rounded once to FP32.  Degree-1
+// columns end in B1 (the caller converts them back from there).
 void filter32_block(const C *Hc, int64_t N, C *V, C *B1, int64_t ld, int n,
                     const int *deg, double mu1, double alpha, double beta,
                     C *fpart, hipStream_t s, std::vector<hipEvent_t> *prof) {
@@ -462,7 +477,8 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
 
     const int cap = degree_cap(p.degree_max);
     int d0 = std::min(std::max(2, o.initial_degree), cap);
-    d0 += d0 % 2;
+    d0 += d0 % 2;   // cap is even here unless it is 1
+    if (cap == 1) d0 = 1;
     std::vector<int> deg(ne, d0), hperm(ne);
     std::vector<double> lam(ne, 0.0), res(ne, INFINITY);
     // Mixed precision: a column is filtered in FP32 while its residual is
@@ -500,19 +516,23 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
                 z2c_block(V + L, ne, Vc, n32, N, n32, s);
                 filter32_block(Hc, N, Vc, Bc, n32, n32, deg.data() + L, mu1, alpha,
                                beta, fpart32, s, prof32p);
-                c2z_block(Vc, n32, V + L, ne, N, n32, s);
+                const int n1 = degree_one_count(deg.data() + L, n32);
+                c2z_block(Bc, n32, V + L, ne, N, n1, s);
+                c2z_block(Vc + n1, n32, V + L + n1, ne, N, n32 - n1, s);
                 for (int j = L; j < L + n32; ++j) info.matvecs_filter_fp32 += deg[j];
             }
             if (n - n32 > 0) {
                 info.filter_bytes += (double)deg[ne - 1] * 16.0 * Nd * Nd;
                 for (int j = L + n32; j < ne; ++j) info.filter_bytes += 48.0 * Nd * deg[j];
             }
-            if (p.sink)
+            if (p.sink) {
                 p.sink->run(filter_steps(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne,
                                          n - n32, deg.data() + L + n32, mu1, alpha, beta,
                                          fpart),
                             s);
-            else
+                finish_degree_one(V + L + n32, B1 + L + n32, ne, N, n - n32,
+                                  deg.data() + L + n32, s);
+            } else
                 filter_block(p.H, p.ldh, N, V + L + n32, B1 + L + n32, ne, n - n32,
                              deg.data() + L + n32, mu1, alpha, beta, fpart, s, profp);
             for (int j = L; j < ne; ++j) info.matvecs_filter += deg[j];

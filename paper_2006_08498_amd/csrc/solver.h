@@ -57,6 +57,19 @@ std::vector<FilterCall> filter_steps(const Z *H, int64_t ldh, int64_t N, Z *V, Z
                                      int64_t ld, int n, const int *deg, double mu1,
                                      double alpha, double beta, Z *fpart);
 
+// Argument checks of a solve, before any device work (throw Error with
+// CHASE_EINVAL): sizes, tol, degree_max and the options.  Shared by the
+// solve calls and the server's submissions.
+void validate_sizes(int64_t N, int32_t nev, int32_t nex);
+void validate_opts(const chase_opts &o);
+void validate_problem(int64_t N, int32_t nev, int32_t nex, double tol, int32_t degree_max,
+                      const chase_opts &o);
+
+// Copies the leading degree-1 columns of a filtered block (deg ascending)
+// from B1, where a one-step recurrence leaves them, back to V.
+void finish_degree_one(Z *V, const Z *B1, int64_t ld, int64_t N, int n, const int *deg,
+                       hipStream_t s);
+
 // Step-level helpers shared with the C ABI.
 void filter_block(const Z *H, int64_t ldh, int64_t N, Z *V, Z *B1, int64_t ld,
                   int n, const int *deg, double mu1, double alpha, double beta,

@@ -59,7 +59,8 @@ def test_defaults():
     ((10, 0, 0, 1e-10, 20), "nev must be"),
     ((10, 2, -1, 1e-10, 20), "nex must be"),
     ((10, 2, 1, 0.0, 20), "tol"),
-    ((10, 2, 1, 1e-10, 1), "degree_max"),
+    ((10, 2, 1, 1e-10, 0), "degree_max"),
+    ((10, 2, 1, float("inf"), 20), "tol"),
     ((10, 2, 1, 1e-10, 65), "degree_max"),
 ])
 def test_invalid_arguments_rejected_before_device_work(args, msg):

@@ -81,3 +81,19 @@ def test_serve_roofline_is_flops_over_the_makespan():
     assert abs(roof["achieved"] - 8e15 / 100.0 / 1e12) < 1e-9
     assert abs(roof["per_launch_tflops_while_sharing"] - 8e15 / 200.0 / 1e12) < 1e-9
     assert roof["launches"] == 100
+
+
+def test_cpu_baseline_is_marked_extrapolated_with_fit_points():
+    """The oracle timed on a bounded sample: a value scaled past the sample
+    says so, and carries the three measured fit points and their exponent."""
+    import bench
+    w = dict(kind="dk", N=24000, nev=20, std=0.02, decay=200.0)
+    out = bench.cpu_baseline(w, 0, budget_s=0.3)
+    assert out["kind"] == "oracle" and out["extrapolated"] is True
+    pts = out["fit_points_n_s"]
+    assert len(pts) == 3 and pts[0][0] < pts[1][0] < pts[2][0] < 24000
+    assert all(t > 0 for _, t in pts)
+    n_s, t_s = pts[-1]
+    assert abs(out["value"] - t_s * (24000 / n_s) ** 3) <= 1e-9 * out["value"]
+    assert 1.0 < out["fit_exponent"] < 4.5
+    assert "not measured" in out["sample"]

@@ -7,7 +7,7 @@ import pytest
 from oracle import eig
 from paper_2006_08498_amd import chase, synth
 from tests.gpu_util import dev_colmajor, host, torch_cuda
-from tests.test_gpu_solve import _check_against_oracle
+from tests.gpu_util import check_against_oracle as _check_against_oracle
 
 pytestmark = pytest.mark.gpu
 

@@ -10,53 +10,10 @@ import pytest
 
 from oracle import brute, eig
 from paper_2006_08498_amd import chase, synth
+from tests.gpu_util import check_against_oracle as _check_against_oracle
 from tests.gpu_util import dev_colmajor, host, torch_cuda
 
 pytestmark = pytest.mark.gpu
-
-
-def _check_against_oracle(H, res, nev, hn=None):
-    w, V = res.eigvals, host(res.V)
-    N = H.shape[0]
-    m = min(nev + 1, N)
-    w_ext, V_ext = eig.eigh_lowest(H, m)
-    w_ref, V_ref = w_ext[:nev], V_ext[:, :nev]
-    if hn is None:
-        hn = np.abs(np.linalg.eigvalsh(H)).max()
-    assert np.all(np.abs(w - w_ref) <= 1e-10 * np.abs(w_ref) + 1e-300), np.abs(w - w_ref).max()
-    R = H @ V - V * w[None, :]
-    rn = np.linalg.norm(R, axis=0)
-    assert rn.max() / hn <= 1e-10
-    assert np.abs(V.conj().T @ V - np.eye(nev)).max() <= 1e-12
-    # Eigenvectors: group eigenvalues closer than 1e-6 ||H|| into clusters
-    # and compare each cluster's subspace with the oracle's; by Davis-Kahan
-    # each side's angle to the exact subspace is at most its residual norm
-    # over the gap to the rest of the spectrum (a single vector is unique up
-    # to phase).  Computed residuals carry ~sqrt(N) u ||H|| of rounding.
-    rn_ref = np.linalg.norm(H @ V_ref - V_ref * w_ref[None, :], axis=0)
-    floor = 2.0 * np.sqrt(N) * 2.0 ** -53 * hn
-    start = 0
-    while start < nev:
-        end = start + 1
-        while end < nev and w_ref[end] - w_ref[end - 1] <= 1e-6 * hn:
-            end += 1
-        gap = np.inf
-        if start > 0:
-            gap = min(gap, w_ref[start] - w_ref[start - 1])
-        if end < m:
-            gap = min(gap, w_ext[end] - w_ext[end - 1])
-        A, B = V[:, start:end], V_ref[:, start:end]
-        d = np.linalg.norm(A @ (A.conj().T @ B) - B, 2)
-        k = end - start
-        r_both = (np.linalg.norm(rn[start:end]) + np.linalg.norm(rn_ref[start:end])
-                  + 2.0 * np.sqrt(k) * floor)
-        bound = 2.0 * r_both / max(gap, 1e-300) + 1e-13
-        assert d <= bound, (start, end, d, bound)
-        start = end
-    # Phase convention: the entry of largest modulus is real and positive.
-    for j in range(nev):
-        i = np.argmax(np.abs(V[:, j]))
-        assert V[i, j].imag == 0.0 and V[i, j].real > 0.0
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -299,3 +256,44 @@ def test_h_is_read_only_and_padding_is_ignored(precision):
     assert r.status == chase.CHASE_OK
     assert torch.equal(torch.view_as_real(buf).view(torch.int64), before)
     _check_against_oracle(H, r, 8)
+
+
+def test_minimal_chase_solve_call():
+    """chase_solve, the minimal form: null stream, its own workspace, default
+    options; H column-major with ldh = N, V column-major N x nev."""
+    import ctypes
+    torch = torch_cuda()
+    N, nev, nex = 1200, 12, 8
+    H = synth.dk_matrix(N, seed=21)
+    dH = dev_colmajor(H)
+    out = torch.empty((nev, N), dtype=torch.complex128, device="cuda")
+    ev = np.zeros(nev)
+    torch.cuda.synchronize()
+    st = chase.lib().chase_solve(ctypes.c_void_p(dH.data_ptr()), N, nev, nex, 1e-10, 20,
+                                 ev.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.c_void_p(out.data_ptr()))
+    assert st == chase.CHASE_OK, chase.last_error()
+    res = chase.SolveResult(ev, out.t(), np.zeros(nev), st)
+    _check_against_oracle(H, res, nev)
+    full = chase.solve(dH, nev, nex, 1e-10, 20)       # chase_solve_ex, defaults
+    assert np.array_equal(full.eigvals, ev)
+    assert np.array_equal(host(full.V), host(out.t()))
+
+
+def test_degree_max_one_single_step_filter():
+    """degree_max = 1: one filter step per iteration (plain subspace
+    iteration with the first Chebyshev polynomial); on a matrix with a wide
+    gap below the unwanted part it still reaches the bar."""
+    torch_cuda()
+    N, nev, nex = 400, 4, 4
+    lam = np.concatenate([[0.1, 0.2, 0.3, 0.4], np.linspace(5.0, 6.0, N - 4)])
+    Q = synth.random_block(N, N, seed=7)
+    Q, _ = np.linalg.qr(Q)
+    H = (Q * lam[None, :]) @ Q.conj().T
+    H = 0.5 * (H + H.conj().T)
+    r = chase.solve(dev_colmajor(H), nev, nex, tol=1e-10, degree_max=1, max_iter=400)
+    assert r.status == chase.CHASE_OK
+    # at most one step per active column per iteration
+    assert 0 < r.info["matvecs_filter"] <= r.info["iterations"] * (nev + nex)
+    _check_against_oracle(H, r, nev)
+    assert np.abs(r.eigvals - lam[:nev]).max() <= 1e-10 * 6.0

@@ -86,12 +86,16 @@ def test_filter_step_group_bitwise_equals_single_steps():
     chase.filter_step_group([])                          # empty group is a no-op
 
 
-def test_filter_per_vector_degrees_vs_oracle_and_closed_form():
+@pytest.mark.parametrize("deg", [[2, 2, 4, 4, 6, 8, 10, 10, 12, 16, 20, 20],
+                                 [1, 1, 1, 2, 2, 4, 6, 6, 8, 10, 12, 14]])
+def test_filter_per_vector_degrees_vs_oracle_and_closed_form(deg):
+    """Per-vector degrees, including degree-1 columns (their single step
+    ends in the other buffer and is copied back)."""
     torch_cuda()
     N = 700
     H, lam, Q = synth.planted_matrix(N, seed=7, n_clusters=4, cluster_size=5)
     V = synth.random_block(N, 12, seed=7)
-    deg = np.array([2, 2, 4, 4, 6, 8, 10, 10, 12, 16, 20, 20])
+    deg = np.array(deg)
     mu1, alpha, beta = lam[0] - 0.01, lam[30], lam[-1] + 0.1
     ref = steps.cheb_filter(H, V, deg, mu1, alpha, beta)
     dV = dev_block(V)

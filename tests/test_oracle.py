@@ -240,6 +240,45 @@ def test_degree_rule_is_minimal_steps():
     assert steps.degree(1.0, tol, 2.5, c, e, 21) == 20    # inside: capped
 
 
+def test_degree_max_one_gives_single_steps():
+    """degree_max = 1 allows one filter step per iteration: every vector,
+    converged or not, gets degree 1, and a degree-1 column of the filter is
+    the first Chebyshev polynomial, C_1(x) = x:  (H - cI) v / (mu1 - c)."""
+    c, e, tol = 6.0, 4.0, 1e-10
+    for lam, res in [(1.5, 1e-2), (1.2, 1e-12), (2.5, 1.0)]:
+        assert steps.degree(res, tol, lam, c, e, 1) == 1
+        assert steps.degree(res, tol, lam, c, e, 2) == 2
+    assert steps.degree_cap(1) == 1 and steps.degree_cap(3) == 2
+    H = synth.dk_matrix(40, seed=2)
+    V = synth.random_block(40, 5, seed=3)
+    mu1, alpha, beta = 0.5, 2.0, 7.0
+    c = 0.5 * (alpha + beta)
+    out = steps.cheb_filter(H, V, [1, 1, 2, 2, 4], mu1, alpha, beta)
+    direct = (H @ V[:, :2] - c * V[:, :2]) / (mu1 - c)
+    assert np.abs(out[:, :2] - direct).max() <= 1e-13 * np.abs(direct).max()
+
+
+def test_orth_against_removes_exactly_the_locked_span():
+    """V = L A + P B with [L P] orthonormal (Householder QR of a complex
+    Gaussian, a library routine): the component of V orthogonal to span(L)
+    is exactly P B.  Complex L, so a missing conjugate or a transposed
+    product fails; V inside span(L) leaves zero; no locked columns leave V."""
+    rng = np.random.default_rng(11)
+    N, k, m = 60, 7, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((N, k + 3)) + 1j * rng.standard_normal((N, k + 3)))
+    L, P = Q[:, :k], Q[:, k:]
+    A = rng.standard_normal((k, m)) + 1j * rng.standard_normal((k, m))
+    B = rng.standard_normal((3, m)) + 1j * rng.standard_normal((3, m))
+    V = L @ A + P @ B
+    out = steps.orth_against(L, V)
+    scale = np.abs(V).max()
+    assert np.abs(out - P @ B).max() <= 1e-14 * N * scale
+    assert np.abs(L.conj().T @ out).max() <= 1e-14 * N * scale
+    assert np.abs(steps.orth_against(L, L @ A)).max() <= 1e-14 * N * np.abs(L @ A).max()
+    assert steps.orth_against(L[:, :0], V) is V
+    assert steps.orth_against(None, V) is V
+
+
 def test_qr_orth_definition():
     V = synth.random_block(70, 9, seed=8)
     Q = steps.qr_orth(V)
