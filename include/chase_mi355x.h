@@ -355,6 +355,24 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
                 void *stream);
 
 /*
+ * chase_heevj without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels in the same order, so
+ * the same bits as chase_heevj, with the working copy of G, the Jacobi
+ * buffers and the eigenvalues (4 n^2 complex + n doubles) in a static
+ * device array of the library of 16 MiB + 64 KiB, which each GPU the
+ * library runs on holds until the process ends.  1 <= n <= 512; a larger n
+ * returns CHASE_EINVAL (use chase_heevj).  Calls no hipMalloc, hipFree or
+ * other allocating routine.  The array keeps the last call's contents
+ * (nothing in it needs clearing: every entry a call reads it writes first).
+ * Overlapping calls on one GPU would race on the array, so the library
+ * serialises them (the call is synchronous); separate processes hold
+ * separate arrays.  Same arguments and results as chase_heevj.
+ */
+int chase_heevj_noalloc(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
+                        void *stream);
+
+/*
  * Filter degrees (host only): for each of n vectors with Ritz value
  * h_theta[j] and residual h_resid[j], the smallest m with
  * rho_j^m >= resid_j / tol_abs (rho_j of the supplement's Eq. S1 on the

@@ -141,6 +141,7 @@ SIGNATURES = {
     "chase_rayleigh_ritz": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _P, _P]),
     "chase_residuals": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _P, _P]),
     "chase_heevj": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
+    "chase_heevj_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "chase_degrees": (ctypes.c_int, [_P, _P, _I32, _D, _D, _D, _I32, _I32, _P]),
     "chase_nex_linear": (_I32, [_I32, _I32, _D, _D, _D]),
     "chase_ingest_rows": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _I64, _P]),
@@ -457,6 +458,23 @@ def heevj(G, stream=None):
     Y = torch.empty_like(G)
     w = np.zeros(n)
     _check(lib().chase_heevj(gp, n, w.ctypes.data_as(_P), _dptr(Y), _stream_ptr(stream)))
+    return w, Y
+
+
+def heevj_noalloc(G, Y=None, stream=None):
+    """heevj through the allocation-free entry point (n <= 512): the library
+    allocates nothing; Y (n, n) may be given to make the call allocation
+    free on the Python side as well."""
+    torch = _torch()
+    n = G.shape[0]
+    gp, ldg = _block(G, "G")
+    if ldg != n:
+        raise ValueError("G must be contiguous")
+    if Y is None:
+        Y = torch.empty_like(G)
+    w = np.zeros(n)
+    _check(lib().chase_heevj_noalloc(gp, n, w.ctypes.data_as(_P), _dptr(Y),
+                                     _stream_ptr(stream)))
     return w, Y
 
 

@@ -511,6 +511,19 @@ int chase_heevj(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
     });
 }
 
+int chase_heevj_noalloc(const chase_z *dG, int32_t n, double *h_w, chase_z *dY,
+                        void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(n >= 1 && n <= kNoAllocMaxOrder,
+                "n must be in [1, " + std::to_string(kNoAllocMaxOrder) +
+                    "] for the allocation-free call (chase_heevj takes up to 1024)");
+        REQUIRE(dG && h_w && dY, "NULL pointer");
+        jacobi_eig_noalloc(reinterpret_cast<const Z *>(dG), n, h_w, reinterpret_cast<Z *>(dY),
+                           S(stream));
+        return CHASE_OK;
+    });
+}
+
 static void validate_ingest(const chase_z *dH, int64_t N, int64_t ldh, const chase_z *rows,
                             int64_t ldr, int64_t r0, int64_t nrows) {
     REQUIRE(N >= 1 && N <= 180000, "N must be in [1, 180000]");

@@ -182,6 +182,12 @@ struct JacobiGraphs {
 size_t jacobi_work_elems(int n);
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
                 hipStream_t s, JacobiGraphs *graphs = nullptr);
+// The same eigensolve (no sweep graphs) with every buffer in a static
+// device array of the library, so that it allocates nothing: G (n x n,
+// not modified) -> h_w (host, ascending) and Y; 1 <= n <= kNoAllocMaxOrder.
+// Synchronous; concurrent calls on one GPU are serialised.
+constexpr int kNoAllocMaxOrder = 512;
+void jacobi_eig_noalloc(const Z *G, int n, double *h_w, Z *Y, hipStream_t s);
 // Symmetrise: G <- (G + G^H)/2, real diagonal.
 void hermitise(Z *G, int n, hipStream_t s);
 

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -580,5 +581,56 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
     check_launch("k_sort_eig");
 }
 
+
+// ------------------------------------------------ allocation-free Jacobi
+// Scratch of jacobi_eig_noalloc: the working copy of G, the three Jacobi
+// buffers and the eigenvalues of one reduced problem of order up to
+// kNoAllocMaxOrder (4 n^2 complex + n doubles = 16 MiB + 4 KiB at 512).
+// Each GPU holds its own copy for the life of the process.  Host code
+// never names the array itself (in host code its name is a host-side
+// stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns on each device.
+constexpr size_t kNoAllocScratchBytes = ((size_t)16 << 20) + ((size_t)64 << 10);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static_assert((size_t)4 * kNoAllocMaxOrder * kNoAllocMaxOrder * sizeof(Z) +
+                      (size_t)kNoAllocMaxOrder * sizeof(double) + 256 <=
+                  kNoAllocScratchBytes,
+              "scratch too small for the largest order");
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu[kNoAllocDevices];    // one solve at a time per GPU
+void *g_noalloc_ptr[kNoAllocDevices] = {};   // device address of scratch
+
+}  // namespace
+
+void jacobi_eig_noalloc(const Z *G, int n, double *h_w, Z *Y, hipStream_t s) {
+    if (n < 1 || n > kNoAllocMaxOrder)
+        throw Error(1, "order " + std::to_string(n) + " exceeds the allocation-free limit of " +
+                           std::to_string(kNoAllocMaxOrder));
+    int dev = -1;
+    CHASE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) throw Error(1, "device index out of range");
+    // Calls are synchronous, so holding the device's lock for the call keeps
+    // concurrent calls on one GPU from sharing the array at the same time.
+    std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        CHASE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(3, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_noalloc_ptr[dev] = p;
+    }
+    char *base = static_cast<char *>(g_noalloc_ptr[dev]);
+    const size_t nn = (size_t)n * n;
+    Z *A = reinterpret_cast<Z *>(base);
+    Z *work = A + nn;                                          // 3 n^2
+    double *w = reinterpret_cast<double *>(work + jacobi_work_elems(n));
+    double hw[4];
+    CHASE_HIP(hipMemcpyAsync(A, G, nn * sizeof(Z), hipMemcpyDeviceToDevice, s));
+    jacobi_eig(A, n, w, Y, work, hw, s, nullptr);
+    CHASE_HIP(hipMemcpyAsync(h_w, w, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    CHASE_HIP(hipStreamSynchronize(s));
+}
 
 }  // namespace chase

@@ -74,6 +74,16 @@ def test_invalid_arguments_rejected_before_device_work(args, msg):
     assert msg in chase.last_error()
 
 
+def test_noalloc_eigensolve_rejects_orders_beyond_its_scratch_before_device_work():
+    L = chase.lib()
+    w = np.zeros(4)
+    for n in (0, 513):
+        st = L.chase_heevj_noalloc(ctypes.c_void_p(16), n, w.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_void_p(16), None)
+        assert st == chase.CHASE_EINVAL
+        assert "allocation-free" in chase.last_error()
+
+
 def test_null_pointers_rejected():
     L = chase.lib()
     ev = np.zeros(2)
