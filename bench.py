@@ -117,9 +117,9 @@ def run_serve(args):
             if res is not None:
                 q = pending.pop(tk)
                 done.append((q, res, time.perf_counter() - t0))
-                if len(done) % 16 == 0:
-                    log(f"{len(done)} done, latency {res.latency_s:.2f} s, "
-                        f"stats {srv.stats()}")
+                log(f"{len(done)} done (N={q['N']}, nev={q['nev']}), latency "
+                    f"{res.latency_s:.2f} s"
+                    + (f", stats {srv.stats()}" if len(done) % 16 == 0 else ""))
         time.sleep(0.002)
     makespan = max(c for _, _, c in done) - sched[0]["t"]
     peak = srv.stats()

@@ -288,6 +288,32 @@ int chase_filter(const chase_z *dH, int64_t N, int64_t ldh,
                  const int32_t *h_degrees, double mu1, double alpha,
                  double beta, int64_t *matvecs, void *stream);
 
+/* One filter call (as chase_filter) of a batch run by chase_filter_fused. */
+typedef struct chase_filter_job {
+    const chase_z *dH;
+    int64_t N, ldh;
+    chase_z *dV;                /* N x n row-major block, filtered in place */
+    int64_t ldv;
+    int32_t n;
+    const int32_t *h_degrees;   /* n degrees, ascending, each 1 or even in [2, 64] */
+    double mu1, alpha, beta;
+} chase_filter_job;
+
+/*
+ * The whole filter calls of several eigenproblems (each with chase_filter's
+ * contract and checks; different H, N and blocks) run by one persistent
+ * kernel: the recurrence steps of all jobs are dealt out as tiles to the
+ * GPU's workgroups as soon as each job's previous step is complete, so the
+ * steps of small problems share the GPU without a launch per step.  This is
+ * the fused form the server uses for concurrent solves
+ * (CHASE_SERVER_FUSE_FILTER).  Each job's result is bitwise the one
+ * chase_filter gives it alone.  count in [0, 4096]; the blocks must not
+ * overlap one another.  *matvecs (may be NULL) receives the total column
+ * products.  Allocates a copy of each block and its scratch.
+ */
+int chase_filter_fused(const chase_filter_job *jobs, int32_t count, int64_t *matvecs,
+                       void *stream);
+
 /*
  * k Lanczos steps from each of the r columns of dV0 (N x r, need not be
  * normalised; not modified).  h_alpha, h_beta: k*r doubles each, row-major
@@ -460,10 +486,13 @@ typedef int (*chase_fill_fn)(chase_z *dH, int64_t N, int64_t ldh, void *user,
 
 /* Server flags. */
 enum {
-    /* Fuse the FP64 filter steps of concurrent solves: one grouped launch
-     * per tick holds the next step of every running solve that is in its
-     * filter phase (chase_filter_step_group), instead of one launch per
-     * step per solve.  Results are bitwise the same either way. */
+    /* Fuse the FP64 filter steps of concurrent small solves (N <= 8192,
+     * whose own launches underfill the GPU): each hands its filter call to
+     * one persistent kernel of the server (the engine behind
+     * chase_filter_fused), which deals out the tiles of all handed-over
+     * calls as each call's previous step completes, instead of one launch
+     * per step per solve; larger solves launch their own.  Results are
+     * bitwise the same either way. */
     CHASE_SERVER_FUSE_FILTER = 1,
     /* Admission order: among the queued requests that fit, the one with
      * the least estimated work (N^2 (nev + nex)) first, instead of arrival
@@ -533,8 +562,9 @@ int chase_server_stats(chase_server *srv, size_t *bytes_in_use,
  * queued request is admitted in arrival order. */
 int chase_server_set_aging(chase_server *srv, double seconds);
 
-/* With CHASE_SERVER_FUSE_FILTER: grouped launches issued so far (ticks)
- * and the filter steps they held; both 0 without fusion. */
+/* With CHASE_SERVER_FUSE_FILTER: launches of the persistent filter kernel
+ * so far (it runs while filter calls are in flight and stops when none is
+ * left) and the filter steps it ran; both 0 without fusion. */
 int chase_server_fusion_stats(chase_server *srv, int64_t *ticks, int64_t *steps);
 
 /* Message for the last server call that failed on this thread. */

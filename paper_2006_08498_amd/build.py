@@ -25,8 +25,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
-SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_filter32.hip", "k_blas.hip", "k_dense.hip",
-           "k_ingest.hip", "control.cpp", "solver.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_filter32.hip", "k_filter_fused.hip",
+           "k_blas.hip", "k_dense.hip", "k_ingest.hip", "control.cpp", "solver.cpp", "capi.cpp",
+           "server.cpp"]
 # Input generators live in a library of their own: they are not the solver.
 SYNTH_SOURCES = ["synth_dev.hip"]
 
@@ -35,7 +36,7 @@ SYNTH_SOURCES = ["synth_dev.hip"]
 # narrower tiles in place; the widest filter tiles need the AGPR file.
 VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 EXTRA = {"k_filter.hip": VGPR_FORM, "k_filter32.hip": VGPR_FORM, "k_blas.hip": VGPR_FORM,
-         "k_dense.hip": VGPR_FORM}
+         "k_dense.hip": VGPR_FORM, "k_filter_fused.hip": VGPR_FORM}
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -135,6 +135,7 @@ SIGNATURES = {
     "chase_shadow_c": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P]),
     "chase_filter": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _P, _D, _D, _D,
                                     ctypes.POINTER(ctypes.c_int64), _P]),
+    "chase_filter_fused": (ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_int64), _P]),
     "chase_lanczos": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _P, _P, _P]),
     "chase_lanczos_bounds": (ctypes.c_int, [_P, _P, _I32, _I32, _I64, _I32, _P]),
     "chase_qr": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, _P]),
@@ -394,6 +395,36 @@ def filter(H, V, degrees, mu1, alpha, beta, stream=None):
     _check(lib().chase_filter(hp, N, ldh, vp, ldv, n, deg.ctypes.data_as(_P),
                               mu1, alpha, beta, ctypes.byref(mv), _stream_ptr(stream)))
     return int(mv.value)
+
+
+class FilterJob(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_void_p), ("N", ctypes.c_int64), ("ldh", ctypes.c_int64),
+                ("dV", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("h_degrees", ctypes.c_void_p), ("mu1", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+def filter_fused(jobs, stream=None):
+    """Several whole filter calls in one persistent launch: ``jobs`` is a
+    list of (H, V, degrees, mu1, alpha, beta) as for ``filter``; every V is
+    filtered in place.  Returns the total column products."""
+    arr = (FilterJob * max(1, len(jobs)))()
+    keep = []
+    for i, (H, V, degrees, mu1, alpha, beta) in enumerate(jobs):
+        hp, ldh = _h_colmajor(H)
+        if V.shape[1] == 0:                 # an empty job: nothing to read
+            vp, ldv = ctypes.c_void_p(None), 0
+        else:
+            vp, ldv = _block(V, "V")
+        d = np.ascontiguousarray(degrees, dtype=np.int32)
+        keep.append(d)
+        arr[i] = FilterJob(hp.value, H.shape[0], ldh, vp.value, ldv, V.shape[1],
+                           d.ctypes.data, mu1, alpha, beta)
+    mv = ctypes.c_int64(0)
+    _check(lib().chase_filter_fused(ctypes.cast(arr, _P), len(jobs), ctypes.byref(mv),
+                                    _stream_ptr(stream)))
+    del keep
+    return mv.value
 
 
 def lanczos(H, V0, k, stream=None):

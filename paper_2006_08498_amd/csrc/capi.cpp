@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "control.h"
+#include "k_filter_fused.h"
 #include "solver.h"
 
 #include <algorithm>
@@ -327,6 +328,73 @@ int chase_filter(const chase_z *dH, int64_t N, int64_t ldh, chase_z *dV,
     });
 }
 
+int chase_filter_fused(const chase_filter_job *jobs, int32_t count, int64_t *matvecs,
+                       void *stream) {
+    return guarded([&]() -> int {
+        REQUIRE(count >= 0 && count <= 4096, "count must be in [0, 4096]");
+        REQUIRE(count == 0 || jobs, "jobs is NULL");
+        int64_t mv = 0;
+        size_t bytes = 0;
+        for (int i = 0; i < count; ++i) {
+            const chase_filter_job &J = jobs[i];
+            REQUIRE(J.N >= 1 && J.N <= (int64_t)1 << 31, "bad N");
+            REQUIRE(J.n >= 0 && J.ldv >= J.n && J.ldh >= J.N, "bad sizes");
+            REQUIRE(J.dH && (J.n == 0 || (J.dV && J.h_degrees)), "NULL pointer");
+            REQUIRE(J.beta > J.alpha && J.mu1 < J.alpha, "need mu1 < alpha < beta");
+            for (int j = 0; j < J.n; ++j) {
+                const int d = J.h_degrees[j];
+                REQUIRE(d == 1 || (d >= 2 && d % 2 == 0 && d <= 64),
+                        "degrees must be 1 or even, in [2, 64]");
+                REQUIRE(j == 0 || d >= J.h_degrees[j - 1], "degrees must be ascending");
+                mv += d;
+            }
+            size_t fp = 0;
+            for (int c = 1; c <= J.n; ++c) fp = std::max(fp, filter_partial_elems(J.N, c));
+            bytes += 2 * (((size_t)J.N * J.n * sizeof(Z) + 255) & ~size_t(255)) +
+                     ((fp * sizeof(Z) + 255) & ~size_t(255));
+        }
+        if (matvecs) *matvecs = mv;
+        if (count == 0 || mv == 0) return CHASE_OK;
+        hipStream_t s = S(stream);
+        DevBuf buf(bytes, s);
+        // Each job on a compact copy (the caller's leading dimension stays
+        // free), with its own second buffer and split-K scratch.
+        std::vector<std::vector<FilterCall>> steps(count);
+        std::vector<Z *> vc(count), b1(count);
+        size_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            const chase_filter_job &J = jobs[i];
+            if (J.n == 0) continue;
+            const size_t blk = ((size_t)J.N * J.n * sizeof(Z) + 255) & ~size_t(255);
+            size_t fp = 0;
+            for (int c = 1; c <= J.n; ++c) fp = std::max(fp, filter_partial_elems(J.N, c));
+            vc[i] = buf.as<Z>(off);
+            b1[i] = buf.as<Z>(off + blk);
+            Z *part = buf.as<Z>(off + 2 * blk);
+            off += 2 * blk + ((fp * sizeof(Z) + 255) & ~size_t(255));
+            copy_block(reinterpret_cast<const Z *>(J.dV), J.ldv, vc[i], J.n, J.N, J.n, s);
+            steps[i] = filter_steps(reinterpret_cast<const Z *>(J.dH), J.ldh, J.N, vc[i], b1[i],
+                                    J.n, J.n, J.h_degrees, J.mu1, J.alpha, J.beta, part);
+        }
+        CHASE_HIP(hipStreamSynchronize(s));   // the engine reads the copies
+        {
+            FilterEngine eng;
+            std::vector<int> slots;
+            for (int i = 0; i < count; ++i)
+                if (jobs[i].n > 0) slots.push_back(eng.submit(steps[i]));
+            for (int sl : slots) eng.wait(sl);
+        }
+        for (int i = 0; i < count; ++i) {
+            const chase_filter_job &J = jobs[i];
+            if (J.n == 0) continue;
+            finish_degree_one(vc[i], b1[i], J.n, J.N, J.n, J.h_degrees, s);
+            copy_block(vc[i], J.n, reinterpret_cast<Z *>(J.dV), J.ldv, J.N, J.n, s);
+        }
+        CHASE_HIP(hipStreamSynchronize(s));
+        return CHASE_OK;
+    });
+}
+
 int chase_lanczos(const chase_z *dH, int64_t N, int64_t ldh,
                   const chase_z *dV0, int64_t ldv0, int32_t r, int32_t k,
                   double *h_alpha, double *h_beta, void *stream) {
@@ -394,14 +462,15 @@ int chase_qr(chase_z *dV, int64_t N, int64_t ldv, int32_t n, int32_t nlocked,
         if (nlocked > 0) gp = std::max(gp, gram_partial_elems(N, nlocked, na));
         const size_t nn = (size_t)n * n;
         const size_t blk = (size_t)N * n * sizeof(Z);
-        DevBuf buf(2 * blk + (gp + 3 * nn + n + 8) * sizeof(Z) + 1024, s);
+        const size_t cwe = chol_work_elems(n);
+        DevBuf buf(2 * blk + (gp + 2 * nn + cwe + 8) * sizeof(Z) + 1024, s);
         Z *Vc = buf.as<Z>();
         Z *B1 = buf.as<Z>(blk);
         Z *gpart = buf.as<Z>(2 * blk);
         Z *G = gpart + gp;
         Z *Bq = G + nn;
         Z *cw = Bq + nn;
-        int *dinfo = reinterpret_cast<int *>(cw + nn + n / 2 + 2);
+        int *dinfo = reinterpret_cast<int *>(cw + cwe + 2);
         copy_block(reinterpret_cast<Z *>(dV), ldv, Vc, n, N, n, s);
         qr_block(Vc, B1, n, N, nlocked, n, G, Bq, cw, gpart, dinfo, s);
         int hinfo[3] = {0, 0, 0};

@@ -153,12 +153,14 @@ void lanczos_update(Z *v, Z *vp, Z *w, int64_t ld, int64_t N, int r,
                     double *alpha, double *beta, int step, int normalise_only,
                     double *scratch, hipStream_t s);
 
-// ------------------------------------------------- small dense (n <= 512)
-// G (n x n Hermitian, row-major ld n) -> in place lower Cholesky factor of
-// D G D + shift I with D = diag(1/sqrt(G_jj)); then writes
-// B = D * L^{-H} (row-major n x n, the right factor for V <- V B).
-// info: device int, set to 1 + column on a non-positive pivot, else 0.
-void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
+// ------------------------------------------------- small dense (n <= 1024)
+// G (n x n Hermitian, row-major ld n, not modified) -> B = D * L^{-H}
+// (row-major n x n, the right factor for V <- V B), L the lower Cholesky
+// factor of D G D + shift I with D = diag(1/sqrt(G_jj)).  work:
+// chol_work_elems(n) complex elements.  info: device int, set to
+// 1 + column on a non-positive pivot, else 0.
+size_t chol_work_elems(int n);
+void chol_qr_factor(const Z *G, int n, double shift, Z *B, Z *work, int *info,
                     hipStream_t s);
 // Reduced Hermitian eigenproblem by cyclic Jacobi.  A: n x n row-major
 // (overwritten).  On return w (device, ascending) and Y (row-major, columns
@@ -171,6 +173,7 @@ struct JacobiGraphs {
         int n;
         const void *A, *work;
         hipGraphExec_t exec[2];
+        int last_sweeps;   // sweeps the previous eigensolve of this order took
     };
     hipStream_t used = nullptr;  // stream the graphs were launched on
     std::vector<Entry> entries;

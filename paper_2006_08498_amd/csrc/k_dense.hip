@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -28,136 +29,76 @@ __device__ __forceinline__ Z zsub(Z a, Z b) { return Z{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------- CholeskyQR
-// CholeskyQR factor, one workgroup of 1024 threads: G (n x n row-major,
-// n <= 1024) -> B = D L^{-H} (upper triangular, row-major) with L the lower
-// Cholesky factor of D G D + shift I and D = diag(G)^{-1/2}.  `work` holds
-// D and X = L^{-1}.  *info = 0, or k + 1 for a non-positive pivot k (then
-// B is not written).  Both halves are right-looking, one step per column:
-//  * Cholesky step k: scale column k by 1/sqrt(pivot), then subtract the
-//    rank-1 product of column k from the trailing lower triangle;
-//  * inversion step k: X[k][j] *= 1/L[k][k] for j <= k, then
-//    X[i][j] -= L[i][k] X[k][j] for i > k, j <= k.
-// Each step's serial input (column k of the updated matrix, with its
-// pivot; row k of X) is handed over through LDS by the previous step's
-// update instead of being re-read from memory, so a step waits on L2 once
-// (its own update) rather than three times.
+// CholeskyQR factor, one workgroup of 8 waves: G (n x n Hermitian,
+// row-major, n <= 1024, not modified) -> B = D L^{-H} (upper triangular,
+// row-major) with L the lower Cholesky factor of W = D G D + shift I and
+// D = diag(G)^{-1/2}, so that V <- V B orthonormalises.  *info = 0, or
+// j + 1 for the first non-positive (or non-finite) pivot j (then B is not
+// written).
+//
+// Blocked in 16 x 16 complex blocks (nt = ceil(n / 16) per side; W is
+// padded with the identity to 16 nt, which leaves L and L^{-1} padded with
+// the identity), right-looking:
+//  * step k: the diagonal block W_kk is factored in LDS (two barriers per
+//    column) and its inverse formed by column-parallel forward
+//    substitution; the panel L_ik = W_ik L_kk^{-H} (i > k) and the trailing
+//    update W_ij -= L_ik L_jk^H (k < j <= i) are 16 x 16 x 16 complex
+//    products on FP64 MFMA, one block per wave at a time;
+//  * then X = L^{-1} by block rows: X_ii = L_ii^{-1} and, for k < i,
+//    X_ik = -L_ii^{-1} sum_{j=k}^{i-1} L_ij X_jk (the sum's result feeds the
+//    second product straight from the accumulator registers).
+// W, X, the diagonal blocks' inverses and D live in `work`
+// (chol_work_elems(n)), L2-resident at these orders.
 
-__global__ __launch_bounds__(1024) void k_chol_factor(Z *G, int n, double shift,
-                                                      Z *B, Z *work,
-                                                      int *info) {
-    __shared__ int bad;
-    __shared__ Z colk[1024], nxt[1024], rowk[1024];
-    __shared__ double ldiag[1024];
-    const int t = threadIdx.x, nt = blockDim.x;
-    double *dsc = reinterpret_cast<double *>(work);          // n doubles
-    Z *X = work + (n + 1) / 2 + 1;                           // n x n
-    if (t == 0) bad = 0x7fffffff;
-    __syncthreads();
-    for (int j = t; j < n; j += nt) {
-        const double gjj = G[(int64_t)j * n + j].x;
-        if (!(gjj > 0.0) || !isfinite(gjj)) atomicMin(&bad, j + 1);   // LDS atomic
-        dsc[j] = gjj > 0.0 ? 1.0 / sqrt(gjj) : 0.0;
-    }
-    __syncthreads();
-    if (bad != 0x7fffffff) {
-        if (t == 0) *info = bad;
-        return;
-    }
-    // Scale and shift (lower triangle only is used below); X = I; column 0
-    // of the scaled matrix into LDS.
-    for (int e = t; e < n * n; e += nt) {
-        const int i = e / n, j = e - i * n;
-        X[e] = Z{i == j ? 1.0 : 0.0, 0.0};
-        if (j > i) continue;
-        Z v = zscale(G[e], dsc[i] * dsc[j]);
-        if (i == j) v = Z{v.x + shift, 0.0};
-        G[e] = v;
-        if (j == 0) nxt[i] = v;
-    }
-    __syncthreads();
-    // Right-looking Cholesky, lower.  nxt holds column k (rows >= k).
-    for (int k = 0; k < n; ++k) {
-        const double piv = nxt[k].x;
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (t == 0) *info = k + 1;
-            return;   // uniform: every thread read the same pivot
-        }
-        const double l = sqrt(piv), il = 1.0 / l;
-        for (int i = k + 1 + t; i < n; i += nt) {
-            const Z v = zscale(nxt[i], il);
-            G[(int64_t)i * n + k] = v;
-            colk[i] = v;
-        }
-        if (t == 0) {
-            G[(int64_t)k * n + k] = Z{l, 0.0};
-            ldiag[k] = l;
-        }
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int e = t; e < m * m; e += nt) {
-            const int ii = e / m, jj = e - ii * m;
-            if (jj > ii) continue;
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            const Z v = zsub(G[(int64_t)i * n + j], zmul(colk[i], zconj(colk[j])));
-            G[(int64_t)i * n + j] = v;
-            if (jj == 0) nxt[i] = v;   // column k + 1 for the next step
-        }
-        __syncthreads();
-    }
-    // X = L^{-1}, right-looking.  rowk holds row k of X (entries <= k);
-    // thread t prefetches L[k + 2 + t][k + 1] for the next step.
-    if (t == 0) nxt[0] = Z{1.0, 0.0};
-    Z lnext = (1 + t < n) ? G[(int64_t)(1 + t) * n + 0] : Z{0.0, 0.0};
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double xkk = 1.0 / ldiag[k];
-        for (int j = t; j <= k; j += nt) {
-            const Z x = zscale(nxt[j], xkk);
-            X[(int64_t)k * n + j] = x;
-            rowk[j] = x;
-        }
-        if (k + 1 + t < n) colk[k + 1 + t] = lnext;
-        if (k + 2 + t < n) lnext = G[(int64_t)(k + 2 + t) * n + (k + 1)];
-        __syncthreads();
-        const int w = k + 1, m = n - k - 1;
-        for (int e = t; e < m * w; e += nt) {
-            const int ii = e / w, j = e - ii * w;
-            const int i = k + 1 + ii;
-            const Z v = zsub(X[(int64_t)i * n + j], zmul(colk[i], rowk[j]));
-            X[(int64_t)i * n + j] = v;
-            if (ii == 0) nxt[j] = v;   // row k + 1 for the next step
-        }
-        if (t == 0 && k + 1 < n) nxt[k + 1] = Z{1.0, 0.0};
-        __syncthreads();
-    }
-    for (int e = t; e < n * n; e += nt) {
-        const int j = e / n, i = e - j * n;   // B row j, column i
-        B[e] = i >= j ? zscale(zconj(X[(int64_t)i * n + j]), dsc[j]) : Z{0.0, 0.0};
-    }
-    if (t == 0) *info = 0;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// The same factor with the matrix held in LDS for orders up to
-// kCholLds: the packed lower triangle (entry (i, j), j <= i, at
-// i (i + 1) / 2 + j; 158 KB at n = 140), one column and the scale factors
-// fit gfx950's 160 KB, so no step waits on L2.  Same operations in the same
-// order as k_chol_factor; X = L^{-1} overwrites L in place (column k of L is
-// saved before row k of X takes its place), and the (row, column) loops run
-// on a 32 x 32 thread grid instead of dividing a flat index.
-constexpr int kCholLds = 140;
+// acc += A B for 16 x 16 complex blocks, K = 16, in the layout of the FP64
+// 16x16x4 MFMA: lane (r, q) = (lane % 16, lane / 16) supplies A[r][4s + q]
+// and B[4s + q][r] at k step s, and register v of its accumulators holds
+// C[q + 4v][r].
+template <class FA, class FB>
+__device__ __forceinline__ void zblock_mac(v4d &cr, v4d &ci, FA a_at, FB b_at) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const Z a = a_at(s), b = b_at(s);
+        cr = mfma64(a.x, b.x, cr);
+        ci = mfma64(a.x, b.y, ci);
+        cr = mfma64(-a.y, b.y, cr);
+        ci = mfma64(a.y, b.x, ci);
+    }
+}
 
-__global__ __launch_bounds__(1024) void k_chol_factor_lds(const Z *G, int n, double shift,
-                                                          Z *B, int *info) {
-    __shared__ Z T[kCholLds * (kCholLds + 1) / 2];
-    __shared__ Z colk[kCholLds];
-    __shared__ double dsc[kCholLds];
+// 8 waves (2 per SIMD): room is left on the CU for other kernels (a
+// 16-wave workgroup of this register size needs a whole idle CU, which a
+// busy GPU rarely has).
+constexpr int kCholThreads = 512;
+
+size_t chol_np(int n) { return (size_t)(n + 15) / 16 * 16; }
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restrict__ G, int n,
+                                                               double shift, Z *__restrict__ B,
+                                                               Z *__restrict__ work,
+                                                               int *info) {
+    __shared__ Z dblk[16][17];   // diagonal block being factored (lower)
+    __shared__ Z linv[16][17];   // its inverse
+    __shared__ double ldg[16];   // its diagonal
     __shared__ int bad;
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int tr = t >> 5, tc = t & 31;
-    auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nwaves = kCholThreads / 64;
+    const int r = lane & 15, q = lane >> 4;
+    const int nt = (n + 15) / 16, np = 16 * nt;
+    Z *W = work;                                  // np x np, row-major
+    Z *X = W + (size_t)np * np;                   // np x np: L^{-1}
+    Z *Li = X + (size_t)np * np;                  // nt blocks of 16 x 16
+    double *dsc = reinterpret_cast<double *>(Li + (size_t)nt * 256);   // np
+
     if (t == 0) bad = 0x7fffffff;
     __syncthreads();
-    for (int j = t; j < n; j += nt) {
+    for (int j = t; j < n; j += kCholThreads) {
         const double gjj = G[(int64_t)j * n + j].x;
         if (!(gjj > 0.0) || !isfinite(gjj)) atomicMin(&bad, j + 1);   // LDS atomic
         dsc[j] = gjj > 0.0 ? 1.0 / sqrt(gjj) : 0.0;
@@ -167,58 +108,131 @@ __global__ __launch_bounds__(1024) void k_chol_factor_lds(const Z *G, int n, dou
         if (t == 0) *info = bad;
         return;
     }
-    for (int i = tr; i < n; i += 32)
-        for (int j = tc; j <= i; j += 32) {
-            Z v = zscale(G[(int64_t)i * n + j], dsc[i] * dsc[j]);
+    // W = D G D + shift I, padded with the identity.
+    for (int64_t e = t; e < (int64_t)np * np; e += kCholThreads) {
+        const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
+        Z v{i == j ? 1.0 : 0.0, 0.0};
+        if (i < n && j < n) {
+            v = zscale(G[(int64_t)i * n + j], dsc[i] * dsc[j]);
             if (i == j) v = Z{v.x + shift, 0.0};
-            T[at(i, j)] = v;
         }
-    __syncthreads();
-    // Right-looking Cholesky, lower.
-    for (int k = 0; k < n; ++k) {
-        const double piv = T[at(k, k)].x;
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (t == 0) *info = k + 1;
-            return;   // uniform: every thread read the same pivot
-        }
-        const double l = sqrt(piv), il = 1.0 / l;
-        __syncthreads();   // the pivot is read everywhere before it is replaced
-        for (int i = k + 1 + t; i < n; i += nt) {
-            const Z v = zscale(T[at(i, k)], il);
-            T[at(i, k)] = v;
-            colk[i] = v;
-        }
-        if (t == 0) T[at(k, k)] = Z{l, 0.0};
-        __syncthreads();
-        for (int i = k + 1 + tr; i < n; i += 32) {
-            const Z ci = colk[i];
-            for (int j = k + 1 + tc; j <= i; j += 32)
-                T[at(i, j)] = zsub(T[at(i, j)], zmul(ci, zconj(colk[j])));
-        }
-        __syncthreads();
+        W[e] = v;
+        X[e] = Z{0.0, 0.0};
     }
-    // X = L^{-1} in place, right-looking: X[k][j] *= 1/L[k][k] (j <= k, with
-    // X[k][k] = 1 before), then X[i][j] -= L[i][k] X[k][j] for i > k
-    // (X[i][k] = 0 before).
-    for (int k = 0; k < n; ++k) {
-        for (int i = k + 1 + t; i < n; i += nt) colk[i] = T[at(i, k)];
-        const double xkk = 1.0 / T[at(k, k)].x;
+    __syncthreads();
+
+    for (int k = 0; k < nt; ++k) {
+        const int64_t kk0 = (int64_t)16 * k;
+        // ---- diagonal block: Cholesky in LDS
+        if (t < 256) {
+            const int i = t >> 4, m = t & 15;
+            dblk[i][m] = m <= i ? W[(kk0 + i) * np + kk0 + m] : Z{0.0, 0.0};
+        }
         __syncthreads();
-        for (int j = t; j <= k; j += nt)
-            T[at(k, j)] = zscale(j == k ? Z{1.0, 0.0} : T[at(k, j)], xkk);
+        for (int j = 0; j < 16; ++j) {
+            const double piv = dblk[j][j].x;
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                if (t == 0) *info = 16 * k + j + 1;
+                return;   // uniform: every thread read the same pivot
+            }
+            const double l = sqrt(piv), il = 1.0 / l;
+            if (t == 0) ldg[j] = l;
+            if (t > j && t < 16) dblk[t][j] = zscale(dblk[t][j], il);
+            __syncthreads();
+            if (t < 256) {
+                const int i = t >> 4, m = t & 15;
+                if (m > j && m <= i) dblk[i][m] = zsub(dblk[i][m], zmul(dblk[i][j], zconj(dblk[m][j])));
+            }
+            __syncthreads();
+        }
+        if (t < 16) dblk[t][t] = Z{ldg[t], 0.0};
         __syncthreads();
-        for (int i = k + 1 + tr; i < n; i += 32) {
-            const Z ci = colk[i];
-            for (int j = tc; j <= k; j += 32) {
-                const Z cur = j == k ? Z{0.0, 0.0} : T[at(i, j)];
-                T[at(i, j)] = zsub(cur, zmul(ci, T[at(k, j)]));
+        // ---- its inverse, one column per thread (forward substitution)
+        if (t < 16) {
+            const int c = t;
+            for (int i = 0; i < 16; ++i) {
+                Z acc{i == c ? 1.0 : 0.0, 0.0};
+                for (int m = c; m < i; ++m) acc = zsub(acc, zmul(dblk[i][m], linv[m][c]));
+                linv[i][c] = i < c ? Z{0.0, 0.0} : zscale(acc, 1.0 / ldg[i]);
             }
         }
         __syncthreads();
+        if (t < 256) {
+            const int i = t >> 4, m = t & 15;
+            Li[(int64_t)k * 256 + i * 16 + m] = linv[i][m];
+            X[(kk0 + i) * np + kk0 + m] = linv[i][m];
+        }
+        // ---- panel: L_ik = W_ik L_kk^{-H}, i > k
+        for (int i = k + 1 + wave; i < nt; i += nwaves) {
+            const Z *Wi = W + (int64_t)16 * i * np + kk0;
+            v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
+            zblock_mac(cr, ci, [&](int s) { return Wi[(int64_t)r * np + 4 * s + q]; },
+                       [&](int s) { return zconj(linv[r][4 * s + q]); });
+            Z *Wo = W + (int64_t)16 * i * np + kk0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Wo[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
+        }
+        __syncthreads();
+        // ---- trailing update: W_ij -= L_ik L_jk^H, k < j <= i
+        const int m = nt - k - 1;
+        const int tiles = m * (m + 1) / 2;
+        for (int tt = wave; tt < tiles; tt += nwaves) {
+            int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+            while (ii * (ii + 1) / 2 > tt) --ii;
+            while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
+            const int jj = tt - ii * (ii + 1) / 2;
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            Z *Wij = W + (int64_t)16 * i * np + 16 * j;
+            const Z *Lik = W + (int64_t)16 * i * np + kk0;
+            const Z *Ljk = W + (int64_t)16 * j * np + kk0;
+            v4d cr, ci;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const Z w = Wij[(int64_t)(q + 4 * v) * np + r];
+                cr[v] = w.x;
+                ci[v] = w.y;
+            }
+            zblock_mac(cr, ci,
+                       [&](int s) {
+                           const Z a = Lik[(int64_t)r * np + 4 * s + q];
+                           return Z{-a.x, -a.y};
+                       },
+                       [&](int s) { return zconj(Ljk[(int64_t)r * np + 4 * s + q]); });
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Wij[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
+        }
+        __syncthreads();
     }
-    for (int j = tr; j < n; j += 32)          // B row j, column i
-        for (int i = tc; i < n; i += 32)
-            B[(int64_t)j * n + i] = i >= j ? zscale(zconj(T[at(i, j)]), dsc[j]) : Z{0.0, 0.0};
+
+    // ---- X = L^{-1} by block rows
+    for (int i = 1; i < nt; ++i) {
+        const Z *Lii = Li + (int64_t)i * 256;
+        for (int k = wave; k < i; k += nwaves) {
+            v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
+            for (int j = k; j < i; ++j) {
+                const Z *Lij = W + (int64_t)16 * i * np + 16 * j;
+                const Z *Xjk = X + (int64_t)16 * j * np + 16 * k;
+                zblock_mac(cr, ci, [&](int s) { return Lij[(int64_t)r * np + 4 * s + q]; },
+                           [&](int s) { return Xjk[(int64_t)(4 * s + q) * np + r]; });
+            }
+            v4d xr{0, 0, 0, 0}, xi{0, 0, 0, 0};
+            zblock_mac(xr, xi,
+                       [&](int s) {
+                           const Z a = Lii[r * 16 + 4 * s + q];
+                           return Z{-a.x, -a.y};
+                       },
+                       [&](int s) { return Z{cr[s], ci[s]}; });
+            Z *Xik = X + (int64_t)16 * i * np + 16 * k;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Xik[(int64_t)(q + 4 * v) * np + r] = Z{xr[v], xi[v]};
+        }
+        __syncthreads();
+    }
+    // ---- B = D X^H (upper triangular), row j, column i
+    for (int64_t e = t; e < (int64_t)n * n; e += kCholThreads) {
+        const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
+        B[e] = i >= j ? zscale(zconj(X[(int64_t)i * np + j]), dsc[j]) : Z{0.0, 0.0};
+    }
     if (t == 0) *info = 0;
 }
 
@@ -336,8 +350,147 @@ __global__ __launch_bounds__(256) void k_jacobi_round(
     }
 }
 
+// The whole cyclic Jacobi of a small reduced problem in one launch of one
+// workgroup, with the convergence test (the host's: off <= 1e-15 tot, or
+// off <= 1e-12 tot and no longer halving) on the device, so a solve's
+// eigensolve is one launch instead of one per round (under concurrent
+// solves each of those launches waits for room on the GPU).  Each round
+// computes the m / 2 rotations, then applies them in place to every 2 x 2
+// block (pa, qa) x (pb, qb) of A and to the pairs of columns of V (every
+// block and column pair is owned by one thread, so no entry is read after
+// another thread wrote it), and each sweep ends with the off-diagonal norm.
+// Then w (ascending, ties by index) and Y[:, rank] = V[:, j].  *status =
+// sweeps done, -1 if the cap was reached without convergence, -2 on a
+// non-finite norm.  A and V (n x n row-major) live in LDS, up to
+// kJacobiLds.  (The same sweeps with A and V in L2 for orders up to 320
+// were measured and not kept: at n = 140 the one workgroup took 10 ms per
+// eigensolve against 4 ms for the round launches of the sweep graphs.)
+constexpr int kJacobiLds = 64;
+
+__device__ __forceinline__ void jacobi_all_sweeps(const Z *__restrict__ A0, Z *As, Z *Vs,
+                                                  Rot *rot, double (*red)[1024], int n,
+                                                  int max_sweeps, double *__restrict__ w,
+                                                  Z *__restrict__ Y, int *status) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int m = n + (n & 1), h = m / 2;
+    for (int e = t; e < n * n; e += nt) {
+        As[e] = A0[e];
+        Vs[e] = Z{(e / n) == (e % n) ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    double prev = 1e300;
+    int result = -1;
+    for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+        for (int round = 0; round < m - 1; ++round) {
+            for (int k = t; k < h; k += nt) {
+                int p, q;
+                rr_pair(m, round, k, p, q);
+                rot[k] = make_rot(As, n, p, q);
+            }
+            __syncthreads();
+            for (int e = t; e < h * h + n * h; e += nt) {
+                if (e < h * h) {
+                    const int ka = e / h, kb = e - ka * h;
+                    int pa, qa, pb, qb;
+                    rr_pair(m, round, ka, pa, qa);
+                    rr_pair(m, round, kb, pb, qb);
+                    const Rot Ra = rot[ka], Rb = rot[kb];
+                    const bool qa_ok = qa < n, qb_ok = qb < n;
+                    if (ka == kb) {
+                        As[pa * n + pa] = Z{Ra.dp, 0.0};
+                        if (qa_ok) {
+                            As[qa * n + qa] = Z{Ra.dq, 0.0};
+                            if (Ra.active) As[pa * n + qa] = As[qa * n + pa] = Z{0.0, 0.0};
+                        }
+                        continue;
+                    }
+                    const Z zero{0.0, 0.0};
+                    const Z m00 = As[pa * n + pb];
+                    const Z m01 = qb_ok ? As[pa * n + qb] : zero;
+                    const Z m10 = qa_ok ? As[qa * n + pb] : zero;
+                    const Z m11 = (qa_ok && qb_ok) ? As[qa * n + qb] : zero;
+                    const Z j00b{Rb.c, 0.0}, j01b{Rb.s, 0.0};
+                    const Z j10b = zscale(Rb.e, -Rb.s), j11b = zscale(Rb.e, Rb.c);
+                    const Z t00 = zadd(zmul(m00, j00b), zmul(m01, j10b));
+                    const Z t01 = zadd(zmul(m00, j01b), zmul(m01, j11b));
+                    const Z t10 = zadd(zmul(m10, j00b), zmul(m11, j10b));
+                    const Z t11 = zadd(zmul(m10, j01b), zmul(m11, j11b));
+                    const Z c00{Ra.c, 0.0}, c10 = zconj(zscale(Ra.e, -Ra.s));
+                    const Z c01{Ra.s, 0.0}, c11 = zconj(zscale(Ra.e, Ra.c));
+                    As[pa * n + pb] = zadd(zmul(c00, t00), zmul(c10, t10));
+                    if (qb_ok) As[pa * n + qb] = zadd(zmul(c00, t01), zmul(c10, t11));
+                    if (qa_ok) As[qa * n + pb] = zadd(zmul(c01, t00), zmul(c11, t10));
+                    if (qa_ok && qb_ok) As[qa * n + qb] = zadd(zmul(c01, t01), zmul(c11, t11));
+                } else {
+                    const int u = e - h * h;
+                    const int i = u / h, kb = u - i * h;
+                    int pb, qb;
+                    rr_pair(m, round, kb, pb, qb);
+                    if (qb >= n) continue;
+                    const Rot Rb = rot[kb];
+                    const Z vp = Vs[i * n + pb], vq = Vs[i * n + qb];
+                    const Z j10b = zscale(Rb.e, -Rb.s), j11b = zscale(Rb.e, Rb.c);
+                    Vs[i * n + pb] = zadd(zscale(vp, Rb.c), zmul(vq, j10b));
+                    Vs[i * n + qb] = zadd(zscale(vp, Rb.s), zmul(vq, j11b));
+                }
+            }
+            __syncthreads();
+        }
+        double off = 0.0, tot = 0.0;
+        for (int e = t; e < n * n; e += nt) {
+            const Z v = As[e];
+            const double mm = v.x * v.x + v.y * v.y;
+            tot += mm;
+            if (e / n != e % n) off += mm;
+        }
+        red[0][t] = off;
+        red[1][t] = tot;
+        __syncthreads();
+        for (int st = nt / 2; st > 0; st >>= 1) {
+            if (t < st) {
+                red[0][t] += red[0][t + st];
+                red[1][t] += red[1][t + st];
+            }
+            __syncthreads();
+        }
+        const double o = sqrt(red[0][0]), tt = sqrt(red[1][0]);
+        __syncthreads();   // red is reused by the next sweep
+        if (!isfinite(o)) {
+            result = -2;
+            break;
+        }
+        if (o <= 1e-15 * tt || (o <= 1e-12 * tt && o >= 0.5 * prev)) {
+            result = sweep + 1;
+            break;
+        }
+        prev = o;
+    }
+    if (n == 1) result = 0;
+    for (int j = t; j < n; j += nt) {
+        const double dj = As[j * n + j].x;
+        int rank = 0;
+        for (int i = 0; i < n; ++i) {
+            const double di = As[i * n + i].x;
+            rank += (di < dj) || (di == dj && i < j);
+        }
+        w[rank] = dj;
+        for (int i = 0; i < n; ++i) Y[(int64_t)i * n + rank] = Vs[i * n + j];
+    }
+    if (t == 0) *status = result;
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_small(const Z *__restrict__ A0, int n,
+                                                       int max_sweeps, double *__restrict__ w,
+                                                       Z *__restrict__ Y, int *status) {
+    __shared__ Z As[kJacobiLds * kJacobiLds];
+    __shared__ Z Vs[kJacobiLds * kJacobiLds];
+    __shared__ Rot rot[kJacobiLds / 2];
+    __shared__ double red[2][1024];
+    jacobi_all_sweeps(A0, As, Vs, rot, red, n, max_sweeps, w, Y, status);
+}
+
 // off^2 = sum_{i != j} |A_ij|^2 and tot^2 = sum |A_ij|^2 (one workgroup,
-// fixed order).
+// fixed order) into out[0..1]; out[2..3] get what out[0..1] held.
 __global__ __launch_bounds__(1024) void k_offnorm(const Z *__restrict__ A,
                                                   int n, double *out) {
     __shared__ double s1[1024], s2[1024];
@@ -361,6 +514,11 @@ __global__ __launch_bounds__(1024) void k_offnorm(const Z *__restrict__ A,
         __syncthreads();
     }
     if (t == 0) {
+        // The previous sweep's norms move to out[2..3], so a batch of sweeps
+        // checked at once still has the last two.
+        const double o0 = out[0], o1 = out[1];
+        out[2] = o0;
+        out[3] = o1;
         out[0] = s1[0];
         out[1] = s2[0];
     }
@@ -415,17 +573,17 @@ inline int grid_for(int64_t total) {
 
 }  // namespace
 
-void chol_qr_factor(Z *G, int n, double shift, Z *B, Z *work, int *info,
+size_t chol_work_elems(int n) {
+    const size_t np = chol_np(n), nt = np / 16;
+    return 2 * np * np + nt * 256 + (np + 1) / 2 + 1;
+}
+
+void chol_qr_factor(const Z *G, int n, double shift, Z *B, Z *work, int *info,
                     hipStream_t s) {
-    if (n <= kCholLds) {
-        hipLaunchKernelGGL(k_chol_factor_lds, dim3(1), dim3(1024), 0, s, (const Z *)G, n, shift,
-                           B, info);
-        check_launch("k_chol_factor_lds");
-        return;
-    }
-    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, G, n, shift, B, work,
+    if (n < 1 || n > 1024) throw Error(7, "chol_qr_factor: order out of range");
+    hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(kCholThreads), 0, s, G, n, shift, B, work,
                        info);
-    check_launch("k_chol_factor");
+    check_launch("k_chol_blocked");
 }
 
 size_t jacobi_work_elems(int n) { return (size_t)3 * n * n; }
@@ -488,7 +646,7 @@ const hipGraphExec_t *sweep_graphs(JacobiGraphs &g, Z *A, Z *A2, Z *V, Z *V2, in
                                    int grid, double *dnorm, Z *work) {
     for (auto &e : g.entries)
         if (e.n == n && e.A == A && e.work == work) return e.exec;
-    JacobiGraphs::Entry e{n, A, work, {nullptr, nullptr}};
+    JacobiGraphs::Entry e{n, A, work, {nullptr, nullptr}, 0};
     for (int par = 0; par < 2; ++par) {
         hipGraph_t gr = nullptr;
         CHASE_HIP(hipGraphCreate(&gr, 0));
@@ -526,8 +684,48 @@ const hipGraphExec_t *sweep_graphs(JacobiGraphs &g, Z *A, Z *A2, Z *V, Z *V2, in
 
 }  // namespace
 
+// Sweeps the last problem of this order and buffer set needed (0 before the
+// first); the entry exists once sweep_graphs has built it.
+static int *graphs_last_sweeps(JacobiGraphs &g, const Z *A, int n, const Z *work) {
+    for (auto &e : g.entries)
+        if (e.n == n && e.A == A && e.work == work) return &e.last_sweeps;
+    return nullptr;
+}
+
+static int jacobi_max_sweeps() {
+    // Cyclic Jacobi converges quadratically (a few sweeps to the rounding
+    // floor at these orders); a diagnostic override of the cap lets the
+    // failure path be exercised.
+    int max_sweeps = 30;
+    if (const char *e = std::getenv("CHASE_JACOBI_MAX_SWEEPS")) {
+        const int v = std::atoi(e);
+        if (v >= 1) max_sweeps = v;
+    }
+    return max_sweeps;
+}
+
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
                 hipStream_t s, JacobiGraphs *graphs) {
+    if (n <= kJacobiLds) {
+        // One launch, no host round trip per sweep; the status word lives
+        // in the (otherwise unused) work buffer.  At most 8 waves, so that
+        // the launch fits beside other kernels.
+        const int max_sweeps = jacobi_max_sweeps();
+        int *dstatus = reinterpret_cast<int *>(work);
+        const int threads = n <= 32 ? 256 : 512;
+        hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(threads), 0, s, (const Z *)A, n,
+                           max_sweeps, w, Y, dstatus);
+        check_launch("k_jacobi_small");
+        CHASE_HIP(hipMemcpyAsync(hwork, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        int st = 0;
+        std::memcpy(&st, hwork, sizeof(int));
+        if (st == -2) throw Error(5, "jacobi: non-finite matrix");
+        if (st == -1)
+            throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
+                               std::to_string(max_sweeps) + " sweeps");
+        return;
+    }
     Z *A2 = work;
     Z *V = work + (size_t)n * n;
     Z *V2 = work + (size_t)2 * n * n;
@@ -542,36 +740,43 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
         const hipGraphExec_t *ex =
             graphs ? sweep_graphs(*graphs, A, A2, V, V2, n, m, grid, dnorm, work) : nullptr;
         double prev = 1e300;
-        // Cyclic Jacobi converges quadratically (a few sweeps to the rounding
-        // floor at these orders); a diagnostic override of the cap lets the
-        // failure path be exercised.
-        int max_sweeps = 30;
-        if (const char *e = std::getenv("CHASE_JACOBI_MAX_SWEEPS")) {
-            const int v = std::atoi(e);
-            if (v >= 1) max_sweeps = v;
-        }
+        const int max_sweeps = jacobi_max_sweeps();
         bool converged = false;
-        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-            // m - 1 (odd) rounds: each sweep leaves the result in the other
-            // buffer of the pair, so consecutive sweeps alternate parity.
-            if (ex) {
-                graphs->used = s;
-                CHASE_HIP(hipGraphLaunch(ex[sweep & 1], s));
+        // With sweep graphs, the first check comes after one sweep fewer
+        // than the previous problem of this order needed (the reduced
+        // problems of consecutive iterations are alike), then after every
+        // sweep: fewer host round trips, a sweep more at most.
+        int *last = graphs ? graphs_last_sweeps(*graphs, A, n, work) : nullptr;
+        int batch = last ? std::max(1, *last - 1) : 1;
+        int sweep = 0;
+        while (sweep < max_sweeps) {
+            const int b = std::min(batch, max_sweeps - sweep);
+            for (int i = 0; i < b; ++i, ++sweep) {
+                // m - 1 (odd) rounds: each sweep leaves the result in the
+                // other buffer of the pair, so consecutive sweeps alternate
+                // parity.
+                if (ex) {
+                    graphs->used = s;
+                    CHASE_HIP(hipGraphLaunch(ex[sweep & 1], s));
+                }
+                else launch_sweep(A, A2, V, V2, n, m, grid, dnorm, s);
+                std::swap(A, A2);
+                std::swap(V, V2);
             }
-            else launch_sweep(A, A2, V, V2, n, m, grid, dnorm, s);
-            std::swap(A, A2);
-            std::swap(V, V2);
-            CHASE_HIP(hipMemcpyAsync(hwork, dnorm, 2 * sizeof(double),
+            CHASE_HIP(hipMemcpyAsync(hwork, dnorm, 4 * sizeof(double),
                                      hipMemcpyDeviceToHost, s));
             CHASE_HIP(hipStreamSynchronize(s));
             const double off = std::sqrt(hwork[0]), tot = std::sqrt(hwork[1]);
+            if (b >= 2) prev = std::sqrt(hwork[2]);   // the sweep before the last
             if (!std::isfinite(off)) throw Error(5, "jacobi: non-finite matrix");
             if (off <= 1e-15 * tot || (off <= 1e-12 * tot && off >= 0.5 * prev)) {
                 converged = true;   // tiny, or at the rounding floor
                 break;
             }
             prev = off;
+            batch = 1;
         }
+        if (last) *last = sweep;
         if (!converged)
             throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
                                std::to_string(max_sweeps) + " sweeps");

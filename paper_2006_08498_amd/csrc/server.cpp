@@ -9,6 +9,7 @@
 #include "../../include/chase_mi355x.h"
 
 #include "common.h"
+#include "k_filter_fused.h"
 #include "solver.h"
 
 #include <algorithm>
@@ -56,163 +57,39 @@ struct Request {
     bool collecting = false;   // a poll is copying the result out
 };
 
-// Cross-request filter fusion.  Each running solve hands the FP64 filter
-// steps of an iteration to the broker (FilterSink::run) instead of
-// launching them.  The broker thread issues ticks on its own stream: a tick
-// is one grouped launch (filter_gemm_group) holding the next step of every
-// solve whose steps are queued, so the tiles of several small problems
-// share one grid.  A solve joins at the next tick once the work before its
-// filter (on its own stream) has finished, and its stream waits for the
-// tick that holds its last step.  At most two ticks are in flight, so a
-// solve that becomes ready waits at most two ticks to join.
-class Broker final : public FilterSink {
-  public:
-    explicit Broker(int device) : device_(device) {
-        CHASE_HIP(hipStreamCreateWithFlags(&fs_, hipStreamNonBlocking));
-        for (auto &e : tick_) CHASE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        th_ = std::thread([this] { loop(); });
-    }
-    ~Broker() override {
-        {
-            std::lock_guard<std::mutex> lk(m_);
-            stop_ = true;
-        }
-        cv_.notify_all();
-        th_.join();
-        (void)hipStreamSynchronize(fs_);
-        for (auto e : tick_) (void)hipEventDestroy(e);
-        for (auto &kv : ev_) {
-            (void)hipEventDestroy(kv.second.first);
-            (void)hipEventDestroy(kv.second.second);
-        }
-        (void)hipStreamDestroy(fs_);
-    }
+// Cross-request filter fusion.  Each running solve of a small problem
+// (N <= kFuseMaxN) hands the FP64 filter steps of an iteration to the
+// server's persistent filter engine
+// (FilterEngine, k_filter_fused.hip) instead of launching them: one kernel
+// deals out the tiles of every handed-over filter call as soon as each
+// call's previous step is complete, so the steps of concurrent solves share
+// the GPU with no launch per step and no step boundary between problems.
+// The solve's thread waits for its own call only, then goes on with QR on
+// its stream.
+// Orders up to which a served request's filter calls go to the engine.
+constexpr int64_t kFuseMaxN = 8192;
 
-    // Called by the solve running on stream s (one call at a time per
-    // stream); returns once the steps are enqueued and s waits for them.
+class EngineSink final : public FilterSink {
+  public:
     void run(std::vector<FilterCall> &&steps, hipStream_t s) override {
         if (steps.empty()) return;
-        Job j;
-        j.steps = std::move(steps);
-        {
-            // Each stream keeps one (ready, done) event pair for its whole
-            // life: re-recording is safe where destroying an event that a
-            // queued wait still refers to would not be.
-            std::lock_guard<std::mutex> lk(m_);
-            auto it = ev_.find(s);
-            if (it == ev_.end()) {
-                hipEvent_t a = nullptr, b = nullptr;
-                CHASE_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
-                CHASE_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
-                it = ev_.emplace(s, std::make_pair(a, b)).first;
-            }
-            j.ready = it->second.first;
-            j.done = it->second.second;
-        }
-        CHASE_HIP(hipEventRecord(j.ready, s));
-        {
-            std::lock_guard<std::mutex> lk(m_);
-            incoming_.push_back(&j);
-        }
-        cv_.notify_all();
-        {
-            std::unique_lock<std::mutex> lk(m_);
-            cv_job_.wait(lk, [&] { return j.enqueued || j.failed; });
-        }
-        if (j.failed) throw Error(CHASE_EHIP, "fused filter: " + j.error);
-        CHASE_HIP(hipStreamWaitEvent(s, j.done, 0));
-    }
-
-    void stats(int64_t *ticks, int64_t *steps) {
+        // The engine reads the block the work on s produced.
+        CHASE_HIP(hipStreamSynchronize(s));
+        const int slot = eng_.submit(steps);
+        eng_.wait(slot);
         std::lock_guard<std::mutex> lk(m_);
-        *ticks = ticks_;
+        steps_ += (int64_t)steps.size();
+    }
+    void stats(int64_t *launches, int64_t *steps) {
+        eng_.stats(nullptr, nullptr, launches);
+        std::lock_guard<std::mutex> lk(m_);
         *steps = steps_;
     }
 
   private:
-    struct Job {
-        std::vector<FilterCall> steps;
-        size_t next = 0;
-        hipEvent_t ready = nullptr, done = nullptr;
-        bool enqueued = false, failed = false;
-        std::string error;
-    };
-
-    void loop() {
-        (void)hipSetDevice(device_);
-        std::vector<Job *> active;
-        std::vector<FilterCall> calls;
-        int64_t issued = 0;
-        for (;;) {
-            {
-                std::unique_lock<std::mutex> lk(m_);
-                if (active.empty())
-                    cv_.wait_for(lk, std::chrono::microseconds(200),
-                                 [&] { return stop_ || !incoming_.empty(); });
-                if (stop_ && incoming_.empty() && active.empty()) return;
-                // Jobs whose preceding work is complete join this tick.
-                bool woke = false;
-                for (auto it = incoming_.begin(); it != incoming_.end();) {
-                    const hipError_t q = hipEventQuery((*it)->ready);
-                    if (q == hipSuccess) {
-                        active.push_back(*it);
-                        it = incoming_.erase(it);
-                    } else if (q != hipErrorNotReady) {
-                        (*it)->failed = true;
-                        (*it)->error = hipGetErrorString(q);
-                        it = incoming_.erase(it);
-                        woke = true;
-                    } else {
-                        ++it;
-                    }
-                }
-                if (woke) cv_job_.notify_all();
-            }
-            if (active.empty()) {
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-                continue;
-            }
-            try {
-                if (issued >= 2) CHASE_HIP(hipEventSynchronize(tick_[issued % 2]));
-                calls.clear();
-                for (Job *j : active) calls.push_back(j->steps[j->next++]);
-                filter_gemm_group(calls.data(), (int)calls.size(), fs_);
-                CHASE_HIP(hipEventRecord(tick_[issued % 2], fs_));
-                ++issued;
-                std::vector<Job *> still, fin;
-                for (Job *j : active) (j->next == j->steps.size() ? fin : still).push_back(j);
-                for (Job *j : fin) CHASE_HIP(hipEventRecord(j->done, fs_));
-                {
-                    // Once marked, a job belongs to its caller again.
-                    std::lock_guard<std::mutex> lk(m_);
-                    for (Job *j : fin) j->enqueued = true;
-                    ++ticks_;
-                    steps_ += (int64_t)calls.size();
-                }
-                if (!fin.empty()) cv_job_.notify_all();
-                active.swap(still);
-            } catch (const std::exception &e) {
-                std::lock_guard<std::mutex> lk(m_);
-                for (Job *j : active) {
-                    j->failed = true;
-                    j->error = e.what();
-                }
-                active.clear();
-                cv_job_.notify_all();
-            }
-        }
-    }
-
-    int device_;
-    hipStream_t fs_ = nullptr;
-    hipEvent_t tick_[2] = {nullptr, nullptr};
-    std::thread th_;
+    FilterEngine eng_;
     std::mutex m_;
-    std::condition_variable cv_, cv_job_;
-    std::deque<Job *> incoming_;
-    std::map<hipStream_t, std::pair<hipEvent_t, hipEvent_t>> ev_;
-    bool stop_ = false;
-    int64_t ticks_ = 0, steps_ = 0;
+    int64_t steps_ = 0;
 };
 
 }  // namespace
@@ -235,7 +112,7 @@ struct chase_server {
     hipStream_t copy_stream = nullptr;   // poll's result copies (non-blocking)
     std::mutex copy_mu;
     int device = 0;
-    std::unique_ptr<Broker> broker;   // CHASE_SERVER_FUSE_FILTER
+    std::unique_ptr<EngineSink> broker;   // CHASE_SERVER_FUSE_FILTER
 };
 
 namespace {
@@ -302,8 +179,11 @@ void run_one(chase_server *s, Request *r, int slot) {
             }
             H = reinterpret_cast<const Z *>(dH);
         }
-        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts,
-                  s->broker.get()};
+        // Small problems (whose own filter launches underfill the GPU) hand
+        // their filter calls to the persistent engine; large ones launch
+        // their own, which fill the GPU alone.
+        FilterSink *sink = r->N <= kFuseMaxN ? s->broker.get() : nullptr;
+        Problem p{H, r->N, r->N, r->nev, r->nex, r->tol, r->degree_max, r->opts, sink};
         Result R = solve(p, dW, reinterpret_cast<Z *>(dV), r->N, st);
         r->eigvals = std::move(R.eigvals);
         r->resid = std::move(R.resid);
@@ -421,7 +301,7 @@ chase_server *chase_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
             s->streams.push_back(st);
         }
         CHASE_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
-        if (flags & CHASE_SERVER_FUSE_FILTER) s->broker = std::make_unique<Broker>(s->device);
+        if (flags & CHASE_SERVER_FUSE_FILTER) s->broker = std::make_unique<EngineSink>();
         for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker, s, i);
         return s;
     } catch (const std::exception &e) {

@@ -58,7 +58,7 @@ Layout make_layout(int64_t N, int nev, int nex, const chase_opts &o) {
     L.gpart = take(gpart * zb);
     L.G = take(nn * zb);
     L.Bq = take(nn * zb);
-    L.cwork = take(((size_t)(ne + 1) / 2 + 1 + nn) * zb);
+    L.cwork = take(chol_work_elems(ne) * zb);
     L.Y = take(nn * zb);
     L.jwork = take(jacobi_work_elems(ne) * zb);
     L.theta = take((size_t)ne * sizeof(double));

@@ -140,7 +140,10 @@ def test_lanczos_vs_oracle():
                                                  (500, 2, 0, 0), (500, 1, 0, 0),
                                                  (1500, 140, 0, 8), (1500, 141, 0, 0),
                                                  (900, 144, 5, 0), (1000, 60, 0, 12),
-                                                 (1600, 200, 0, 12)])
+                                                 (1600, 200, 0, 12), (800, 16, 0, 0),
+                                                 (800, 17, 0, 4), (900, 15, 2, 0),
+                                                 (2500, 260, 0, 8), (3000, 400, 0, 12),
+                                                 (3000, 400, 140, 8)])
 def test_qr_vs_oracle(N, n, nlocked, graded):
     """graded: column norms fall from 1 to 10^-graded across the block."""
     torch_cuda()
@@ -161,12 +164,12 @@ def test_qr_vs_oracle(N, n, nlocked, graded):
     assert np.abs(Qa.conj().T @ Qa - np.eye(n)).max() <= 1e-14 * np.sqrt(N)
 
 
-@pytest.mark.parametrize("n", [20, 140, 141, 300])
+@pytest.mark.parametrize("n", [20, 140, 141, 300, 1024])
 def test_qr_breakdown_names_the_dependent_column(n):
-    # A zero column has a zero Gram diagonal: both factor kernels (the
-    # LDS-resident one up to 140 columns, the L2 one above) must report it.
+    # A zero column has a zero Gram diagonal, which the factor reports at
+    # its own index whatever the block it falls in.
     torch_cuda()
-    V = synth.random_block(700, n, seed=n)
+    V = synth.random_block(max(700, n + 10), n, seed=n)
     V[:, 7] = 0.0
     with pytest.raises(chase.ChaseError, match="breakdown at column 7"):
         chase.qr(dev_block(V), 0)
@@ -193,8 +196,10 @@ def test_rayleigh_ritz_vs_oracle():
     assert np.abs(V.conj().T @ V - np.eye(n)).max() <= 1e-13
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 141])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 32, 33, 64, 65, 141])
 def test_heevj_vs_oracle(n):
+    """Orders up to 64 take the one-launch LDS kernel, larger ones the
+    per-round launches; both against the oracle."""
     torch_cuda()
     G = synth.random_block(n, n, seed=n)
     G = 0.5 * (G + G.conj().T)
@@ -205,6 +210,18 @@ def test_heevj_vs_oracle(n):
     assert np.abs(w - w_ref).max() <= 1e-13 * gn * max(1.0, np.sqrt(n) / 4)
     assert np.abs(G @ Y - Y * w).max() <= 1e-13 * gn * np.sqrt(n)
     assert np.abs(Y.conj().T @ Y - np.eye(n)).max() <= 1e-13 * np.sqrt(n)
+
+
+def test_heevj_reports_non_convergence(monkeypatch):
+    """A sweep cap below what the matrix needs is reported as an error by
+    both Jacobi paths (the diagnostic override of the cap)."""
+    torch_cuda()
+    monkeypatch.setenv("CHASE_JACOBI_MAX_SWEEPS", "1")
+    for n in (40, 100):
+        G = synth.random_block(n, n, seed=3)
+        G = 0.5 * (G + G.conj().T)
+        with pytest.raises(chase.ChaseError, match="did not converge in 1 sweeps"):
+            chase.heevj(dev_block(G))
 
 
 def test_heevj_degenerate_and_zero():
@@ -246,4 +263,38 @@ def test_device_generator_matches_host_generator():
     G = synth.gaussian_matrix_device(300, 7, seed=2).cpu().numpy()
     Gh = synth.gaussian_matrix(300, 7, seed=2)
     assert np.abs(G - Gh).max() <= 1e-14
+    torch.cuda.synchronize()
+
+
+def test_filter_fused_bitwise_equals_each_job_alone():
+    """Several whole filter calls (different N, column counts over one and
+    several pieces, split and unsplit plans, degree-1 columns) run by the
+    persistent filter engine in one launch: each job's block is bitwise the
+    one chase_filter gives alone; an empty job and a repeat (a second launch
+    of the engine) included."""
+    torch = torch_cuda()
+    specs = [(1000, 40, 3), (2049, 161, 4), (300, 7, 5), (4100, 90, 6), (700, 0, 7),
+             (1536, 16, 8)]
+    jobs, refs = [], []
+    for N, n, seed in specs:
+        H = synth.dk_matrix(N, seed=seed)
+        V = synth.random_block(N, max(n, 1), seed=seed)[:, :n]
+        rng = np.random.default_rng(seed)
+        deg = np.sort(rng.choice([1, 2, 4, 6, 8, 12, 16], size=n)) if n else np.zeros(0, int)
+        lam = np.linalg.eigvalsh(H) if N <= 2049 else None
+        lo, hi = (lam[0], lam[-1]) if lam is not None else (0.8, 6.3)
+        mu1, alpha, beta = lo - 0.01, lo + 0.3 * (hi - lo), hi + 0.1
+        dH = dev_colmajor(H)
+        Vref = dev_block(V)
+        if n:
+            chase.filter(dH, Vref, deg, mu1, alpha, beta)
+        refs.append(host(Vref))
+        jobs.append((dH, dev_block(V), deg, mu1, alpha, beta))
+    for rep in range(2):
+        blocks = [dev_block(r0) for r0 in [host(j[1]) for j in jobs]]
+        mv = chase.filter_fused([(j[0], b, j[2], j[3], j[4], j[5])
+                                 for j, b in zip(jobs, blocks)])
+        assert mv == sum(int(np.sum(j[2])) for j in jobs)
+        for b, r in zip(blocks, refs):
+            assert np.array_equal(host(b), r)
     torch.cuda.synchronize()
