@@ -101,15 +101,18 @@ void c2z_block(const C *Vc, int64_t ldc, Z *V, int64_t ldv, int64_t N, int n,
 
 // C (p x q, row-major ldc) = A^H B over N rows; A: N x p, B: N x q.
 // `part` holds gram_partial_elems(N, p, q) elements of split-K partials.
+// herm (requires A = B): only the tiles on and above the diagonal are
+// computed and C is made Hermitian to the last bit (real diagonal).
 size_t gram_partial_elems(int64_t N, int p, int q);
 void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N, int p,
-          int q, Z *C, int64_t ldc, Z *part, hipStream_t s);
+          int q, Z *C, int64_t ldc, Z *part, hipStream_t s, bool herm = false);
 
 // C (N x q) = alpha * A (N x p) * B (p x q, row-major ldb) + beta * C0.
-// C0 may alias C or be null (beta == 0).  C must not overlap A.
+// C0 may alias C or be null (beta == 0).  C must not overlap A.  upper: B is
+// upper triangular (rows below each column's diagonal are skipped).
 void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N, int p,
           int q, double alpha, const Z *C0, int64_t ldc0, double beta, Z *C,
-          int64_t ldc, hipStream_t s);
+          int64_t ldc, hipStream_t s, bool upper = false);
 
 // Column norms of (V - V2 * diag(theta)) or of V (V2 == null); deterministic
 // two-pass reduction.  out: n doubles on the device.  part: norm_partial_elems.
@@ -183,8 +186,13 @@ struct JacobiGraphs {
     ~JacobiGraphs();
 };
 size_t jacobi_work_elems(int n);
+// hstatus (pinned host int, optional): for the one-launch path (n <=
+// kJacobiLds) the convergence status is copied there and not checked, so
+// the call returns without waiting for the stream; the caller passes it to
+// jacobi_check_status after its next synchronisation.
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
-                hipStream_t s, JacobiGraphs *graphs = nullptr);
+                hipStream_t s, JacobiGraphs *graphs = nullptr, int *hstatus = nullptr);
+void jacobi_check_status(int n, int status);
 // The same eigensolve (no sweep graphs) with every buffer in a static
 // device array of the library, so that it allocates nothing: G (n x n,
 // not modified) -> h_w (host, ascending) and Y; 1 <= n <= kNoAllocMaxOrder.

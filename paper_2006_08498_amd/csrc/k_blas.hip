@@ -19,13 +19,15 @@ __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
 // part[s] (p x q) = sum over rows of chunk s of conj(A[i, :])^T B[i, :].
 // Workgroup = 4 waves over interleaved 4-row steps of the chunk, one
 // 16 x 16*WN tile of C; the four wave sums are added in LDS in wave order.
+// herm (A = B, a Hermitian result): tiles wholly below the diagonal are
+// skipped; the partial sums fill them from their mirror images.
 template <int WN>
 __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
                                               int64_t lda,
                                               const Z *__restrict__ B,
                                               int64_t ldb, int N, int p, int q,
                                               int pb, int qb, int chunk,
-                                              Z *__restrict__ part) {
+                                              Z *__restrict__ part, int herm) {
     __shared__ double red[3][64 * 8 * WN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, qq = lane >> 4;
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
     const int jb = t % qb;
     const int s = t / qb;
     const int p0 = ib * 16, q0 = jb * 16 * WN;
+    if (herm && q0 + 16 * WN <= p0) return;   // uniform: whole workgroup
     const int kbeg = s * chunk, kend = min(N, kbeg + chunk);
     const int acol = min(p0 + r, p - 1);
     int bcol[WN];
@@ -96,19 +99,30 @@ __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
     }
 }
 
+// C = sum of the partials in a fixed order.  herm: only the entries on and
+// above the diagonal are summed; each sets its mirror to the conjugate and
+// a diagonal entry is made real, so C is Hermitian to the last bit.
 __global__ void k_sum_parts(const Z *__restrict__ part, int nparts, int p,
-                            int q, Z *__restrict__ C, int64_t ldc) {
+                            int q, Z *__restrict__ C, int64_t ldc, int herm) {
     const int64_t total = (int64_t)p * q;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / q, j = t - i * q;
+        if (herm && i > j) continue;
         double sr = 0.0, si = 0.0;
         for (int s = 0; s < nparts; ++s) {
             const Z v = part[(int64_t)s * total + t];
             sr += v.x;
             si += v.y;
         }
-        const int64_t i = t / q, j = t - i * q;
-        C[i * ldc + j] = Z{sr, si};
+        if (!herm) {
+            C[i * ldc + j] = Z{sr, si};
+        } else if (i == j) {
+            C[i * ldc + j] = Z{sr, 0.0};
+        } else {
+            C[i * ldc + j] = Z{sr, si};
+            C[j * ldc + i] = Z{sr, -si};
+        }
     }
 }
 
@@ -135,20 +149,22 @@ GramPlan gram_plan(int64_t N, int p, int q) {
 
 template <int WN>
 void launch_gram(const GramPlan &g, const Z *A, int64_t lda, const Z *B,
-                 int64_t ldb, int N, int p, int q, Z *part, hipStream_t s) {
+                 int64_t ldb, int N, int p, int q, Z *part, int herm, hipStream_t s) {
     const int blocks = g.pb * g.qb * g.chunks;
     hipLaunchKernelGGL(k_gram<WN>, dim3(blocks), dim3(256), 0, s, A, lda, B,
-                       ldb, N, p, q, g.pb, g.qb, g.chunk, part);
+                       ldb, N, p, q, g.pb, g.qb, g.chunk, part, herm);
 }
 
 // ------------------------------------------------------------------ tsmm
 // C (N x q) = alpha * A (N x p) B (p x q) + beta * C0; wave = 16 rows x
 // 16*WN columns, K = p.
+// upper: B is upper triangular, so a column block's sum stops at its last
+// column (the rows below are zero).
 template <int WN>
 __global__ __launch_bounds__(256) void k_tsmm(
     const Z *__restrict__ A, int64_t lda, const Z *__restrict__ B, int64_t ldb,
     int N, int p, int q, double alpha, const Z *C0, int64_t ldc0, double beta,
-    Z *C, int64_t ldc, int cb) {
+    Z *C, int64_t ldc, int cb, int upper) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, qq = lane >> 4;
     const int rbk = blockIdx.x / cb, cbk = blockIdx.x % cb;
@@ -166,9 +182,10 @@ __global__ __launch_bounds__(256) void k_tsmm(
         cr[c] = v4d{0, 0, 0, 0};
         ci[c] = v4d{0, 0, 0, 0};
     }
-    for (int k = 0; k < p; k += 4) {
+    const int kmax = upper ? min(p, col0 + 16 * WN) : p;
+    for (int k = 0; k < kmax; k += 4) {
         const int kk = k + qq;
-        const bool ok = kk < p;
+        const bool ok = kk < kmax;
         const int kc = ok ? kk : 0;
         Z a = ap[kc];
         if (!ok) a = Z{0.0, 0.0};
@@ -521,25 +538,27 @@ size_t gram_partial_elems(int64_t N, int p, int q) {
 }
 
 void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
-          int q, Z *C, int64_t ldc, Z *part, hipStream_t s) {
+          int q, Z *C, int64_t ldc, Z *part, hipStream_t s, bool herm) {
     if (p <= 0 || q <= 0) return;
+    if (herm && (A != B || lda != ldb || p != q))
+        throw Error(7, "gram: a Hermitian product needs A = B");
     const int N = (int)N64;
     const GramPlan g = gram_plan(N64, p, q);
     switch (g.wn) {
-#define CASE(w) case w: launch_gram<w>(g, A, lda, B, ldb, N, p, q, part, s); break;
+#define CASE(w) case w: launch_gram<w>(g, A, lda, B, ldb, N, p, q, part, herm ? 1 : 0, s); break;
         CASE(1) CASE(2) CASE(3) CASE(4)
 #undef CASE
         default: throw Error(7, "gram: bad tile width");
     }
     check_launch("k_gram");
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((int64_t)p * q)), dim3(256),
-                       0, s, part, g.chunks, p, q, C, ldc);
+                       0, s, part, g.chunks, p, q, C, ldc, herm ? 1 : 0);
     check_launch("k_sum_parts");
 }
 
 void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
           int q, double alpha, const Z *C0, int64_t ldc0, double beta, Z *C,
-          int64_t ldc, hipStream_t s) {
+          int64_t ldc, hipStream_t s, bool upper) {
     if (N64 <= 0 || q <= 0) return;
     const int N = (int)N64;
     const int nb = (q + 15) / 16;
@@ -551,7 +570,7 @@ void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
 #define CASE(w)                                                                \
     case w:                                                                    \
         hipLaunchKernelGGL(k_tsmm<w>, grid, dim3(256), 0, s, A, lda, B, ldb, N, \
-                           p, q, alpha, C0, ldc0, beta, C, ldc, cb);           \
+                           p, q, alpha, C0, ldc0, beta, C, ldc, cb, upper ? 1 : 0); \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE

@@ -39,9 +39,9 @@ __device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s};
 // Blocked in 16 x 16 complex blocks (nt = ceil(n / 16) per side; W is
 // padded with the identity to 16 nt, which leaves L and L^{-1} padded with
 // the identity), right-looking:
-//  * step k: the diagonal block W_kk is factored in LDS (two barriers per
-//    column) and its inverse formed by column-parallel forward
-//    substitution; the panel L_ik = W_ik L_kk^{-H} (i > k) and the trailing
+//  * step k: the diagonal block W_kk is factored in LDS by one wave and its
+//    inverse formed by column-parallel forward substitution (no workgroup
+//    barrier inside; three per block column in all); the panel L_ik = W_ik L_kk^{-H} (i > k) and the trailing
 //    update W_ij -= L_ik L_jk^H (k < j <= i) are 16 x 16 x 16 complex
 //    products on FP64 MFMA, one block per wave at a time;
 //  * then X = L^{-1} by block rows: X_ii = L_ii^{-1} and, for k < i,
@@ -78,6 +78,13 @@ __device__ __forceinline__ void zblock_mac(v4d &cr, v4d &ci, FA a_at, FB b_at) {
 constexpr int kCholThreads = 512;
 
 size_t chol_np(int n) { return (size_t)(n + 15) / 16 * 16; }
+
+// Orders the LDS accesses of one wave's lanes (no other wave is involved).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restrict__ G, int n,
                                                                double shift, Z *__restrict__ B,
@@ -123,40 +130,52 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
 
     for (int k = 0; k < nt; ++k) {
         const int64_t kk0 = (int64_t)16 * k;
-        // ---- diagonal block: Cholesky in LDS
-        if (t < 256) {
-            const int i = t >> 4, m = t & 15;
-            dblk[i][m] = m <= i ? W[(kk0 + i) * np + kk0 + m] : Z{0.0, 0.0};
+        // ---- diagonal block: Cholesky and inverse in LDS by wave 0 alone
+        // (its lanes order their LDS accesses among themselves; the other
+        // waves wait at the barrier below).
+        if (wave == 0) {
+            for (int e = lane; e < 256; e += 64) {
+                const int i = e >> 4, m = e & 15;
+                dblk[i][m] = m <= i ? W[(kk0 + i) * np + kk0 + m] : Z{0.0, 0.0};
+            }
+            wave_sync();
+            for (int j = 0; j < 16; ++j) {
+                const double piv = dblk[j][j].x;
+                if (!(piv > 0.0) || !isfinite(piv)) {
+                    if (lane == 0) bad = 16 * k + j + 1;
+                    break;   // uniform across the wave: every lane read the same pivot
+                }
+                const double l = sqrt(piv), il = 1.0 / l;
+                if (lane == 0) ldg[j] = l;
+                if (lane > j && lane < 16) dblk[lane][j] = zscale(dblk[lane][j], il);
+                wave_sync();
+                for (int e = lane; e < 256; e += 64) {
+                    const int i = e >> 4, m = e & 15;
+                    if (m > j && m <= i)
+                        dblk[i][m] = zsub(dblk[i][m], zmul(dblk[i][j], zconj(dblk[m][j])));
+                }
+                wave_sync();
+            }
+            wave_sync();
+            if (bad == 0x7fffffff) {
+                if (lane < 16) dblk[lane][lane] = Z{ldg[lane], 0.0};
+                wave_sync();
+                // Inverse, one column per lane (forward substitution).
+                if (lane < 16) {
+                    const int c = lane;
+                    for (int i = 0; i < 16; ++i) {
+                        Z acc{i == c ? 1.0 : 0.0, 0.0};
+                        for (int m = c; m < i; ++m) acc = zsub(acc, zmul(dblk[i][m], linv[m][c]));
+                        linv[i][c] = i < c ? Z{0.0, 0.0} : zscale(acc, 1.0 / ldg[i]);
+                    }
+                }
+            }
         }
         __syncthreads();
-        for (int j = 0; j < 16; ++j) {
-            const double piv = dblk[j][j].x;
-            if (!(piv > 0.0) || !isfinite(piv)) {
-                if (t == 0) *info = 16 * k + j + 1;
-                return;   // uniform: every thread read the same pivot
-            }
-            const double l = sqrt(piv), il = 1.0 / l;
-            if (t == 0) ldg[j] = l;
-            if (t > j && t < 16) dblk[t][j] = zscale(dblk[t][j], il);
-            __syncthreads();
-            if (t < 256) {
-                const int i = t >> 4, m = t & 15;
-                if (m > j && m <= i) dblk[i][m] = zsub(dblk[i][m], zmul(dblk[i][j], zconj(dblk[m][j])));
-            }
-            __syncthreads();
+        if (bad != 0x7fffffff) {
+            if (t == 0) *info = bad;
+            return;   // uniform: every thread reads the flag after the barrier
         }
-        if (t < 16) dblk[t][t] = Z{ldg[t], 0.0};
-        __syncthreads();
-        // ---- its inverse, one column per thread (forward substitution)
-        if (t < 16) {
-            const int c = t;
-            for (int i = 0; i < 16; ++i) {
-                Z acc{i == c ? 1.0 : 0.0, 0.0};
-                for (int m = c; m < i; ++m) acc = zsub(acc, zmul(dblk[i][m], linv[m][c]));
-                linv[i][c] = i < c ? Z{0.0, 0.0} : zscale(acc, 1.0 / ldg[i]);
-            }
-        }
-        __syncthreads();
         if (t < 256) {
             const int i = t >> 4, m = t & 15;
             Li[(int64_t)k * 256 + i * 16 + m] = linv[i][m];
@@ -704,8 +723,16 @@ static int jacobi_max_sweeps() {
     return max_sweeps;
 }
 
+void jacobi_check_status(int n, int st) {
+    if (n > kJacobiLds) return;   // the sweep path checks as it goes
+    if (st == -2) throw Error(5, "jacobi: non-finite matrix");
+    if (st == -1)
+        throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
+                           std::to_string(jacobi_max_sweeps()) + " sweeps");
+}
+
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
-                hipStream_t s, JacobiGraphs *graphs) {
+                hipStream_t s, JacobiGraphs *graphs, int *hstatus) {
     if (n <= kJacobiLds) {
         // One launch, no host round trip per sweep; the status word lives
         // in the (otherwise unused) work buffer.  At most 8 waves, so that
@@ -716,14 +743,15 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
         hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(threads), 0, s, (const Z *)A, n,
                            max_sweeps, w, Y, dstatus);
         check_launch("k_jacobi_small");
+        if (hstatus) {
+            CHASE_HIP(hipMemcpyAsync(hstatus, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+            return;
+        }
         CHASE_HIP(hipMemcpyAsync(hwork, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipStreamSynchronize(s));
         int st = 0;
         std::memcpy(&st, hwork, sizeof(int));
-        if (st == -2) throw Error(5, "jacobi: non-finite matrix");
-        if (st == -1)
-            throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
-                               std::to_string(max_sweeps) + " sweeps");
+        jacobi_check_status(n, st);
         return;
     }
     Z *A2 = work;

@@ -224,15 +224,14 @@ void qr_block(Z *V, Z *B1, int64_t ld, int64_t N, int L, int ne, Z *G, Z *Bq,
     }
     Z *cur = Va, *oth = B1 + L;
     for (int pass = 0; pass < 3; ++pass) {
-        gram(cur, ld, cur, ld, N, n, n, G, n, gpart, s);
-        hermitise(G, n, s);
+        gram(cur, ld, cur, ld, N, n, n, G, n, gpart, s, true);
         // Shift for the scaled Gram matrix (unit diagonal, so trace = n
         // bounds its 2-norm): 11 (N n + n (n + 1)) u ||G||.
         const double u = 1.1102230246251565e-16;
         const double shift =
             pass == 0 ? 11.0 * ((double)N * n + (double)n * (n + 1)) * u * n : 0.0;
         chol_qr_factor(G, n, shift, Bq, cwork, dinfo + pass, s);
-        tsmm(cur, ld, Bq, n, N, n, n, 1.0, nullptr, 0, 0.0, oth, ld, s);
+        tsmm(cur, ld, Bq, n, N, n, n, 1.0, nullptr, 0, 0.0, oth, ld, s, true);
         std::swap(cur, oth);
     }
     if (cur != Va) copy_block(cur, ld, Va, ld, N, n, s);
@@ -260,22 +259,45 @@ void rr_block(const Z *H, int64_t ldh, int64_t N, Z *Q, Z *W, Z *T, Z *B1,
 // Householder QR would then return a roundoff direction for that column.
 // Here the column is replaced by a fresh random vector explicitly and the
 // QR is redone from a backup of the block.  Returns the replaced count.
-static int qr_robust(Z *V, Z *B1, Z *backup, int64_t ld, int64_t N, int L,
-                     int ne, Z *G, Z *Bq, Z *cwork, Z *gpart, int *dinfo,
-                     int *hinfo, uint64_t seed, int &salt, hipStream_t s) {
+//
+// qr_launch enqueues the backup copy, the QR and the copy of its breakdown
+// words to the host (then records `done`); qr_finish waits for `done` only
+// (work enqueued after the QR, such as the next product, keeps the GPU
+// busy meanwhile) and, on a breakdown, redoes the QR from the backup
+// synchronously.  Returns true if it had to redo it.
+static void qr_launch(Z *V, Z *B1, Z *backup, int64_t ld, int64_t N, int L, int ne, Z *G,
+                      Z *Bq, Z *cwork, Z *gpart, int *dinfo, int *hinfo, hipEvent_t done,
+                      hipStream_t s) {
     const int n = ne - L;
-    if (n <= 0) return 0;
+    if (n <= 0) return;
     copy_block(V + L, ld, backup + L, ld, N, n, s);
-    for (int attempt = 0; attempt <= n; ++attempt) {
+    qr_block(V, B1, ld, N, L, ne, G, Bq, cwork, gpart, dinfo, s);
+    CHASE_HIP(hipMemcpyAsync(hinfo, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CHASE_HIP(hipEventRecord(done, s));
+}
+
+static bool qr_finish(Z *V, Z *B1, Z *backup, int64_t ld, int64_t N, int L, int ne, Z *G,
+                      Z *Bq, Z *cwork, Z *gpart, int *dinfo, int *hinfo, hipEvent_t done,
+                      uint64_t seed, int &salt, hipStream_t s) {
+    const int n = ne - L;
+    if (n <= 0) return false;
+    CHASE_HIP(hipEventSynchronize(done));
+    auto first_bad = [&]() {
+        for (int pss = 0; pss < 3; ++pss)
+            if (hinfo[pss] != 0) return hinfo[pss] - 1;
+        return -1;
+    };
+    int bad = first_bad();
+    if (bad < 0) return false;
+    CHASE_HIP(hipStreamSynchronize(s));   // whatever followed the QR is void
+    for (int attempt = 0; attempt < n; ++attempt) {
+        random_block(backup + L + bad, ld, N, 1, seed, 16u + (uint32_t)salt++, s);
+        copy_block(backup + L, ld, V + L, ld, N, n, s);
         qr_block(V, B1, ld, N, L, ne, G, Bq, cwork, gpart, dinfo, s);
         CHASE_HIP(hipMemcpyAsync(hinfo, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipStreamSynchronize(s));
-        int bad = -1;
-        for (int pss = 0; pss < 3 && bad < 0; ++pss)
-            if (hinfo[pss] != 0) bad = hinfo[pss] - 1;
-        if (bad < 0) return attempt;
-        random_block(backup + L + bad, ld, N, 1, seed, 16u + (uint32_t)salt++, s);
-        copy_block(backup + L, ld, V + L, ld, N, n, s);
+        bad = first_bad();
+        if (bad < 0) return true;
     }
     throw Error(CHASE_EINTERNAL, "QR: repeated CholeskyQR breakdown");
 }
@@ -369,8 +391,8 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
     HostBuf hb((size_t)2 * k * r + 4 * (size_t)ne + 16);
     double *h_al = hb.p, *h_be = hb.p + (size_t)k * r;
     double *h_th = h_be + (size_t)k * r, *h_res = h_th + ne;
-    double *h_misc = h_res + ne;   // 4 ints of QR info + Jacobi norms
-    double *h_jac = h_misc + 4;
+    double *h_misc = h_res + ne;   // 3 ints of QR info
+    double *h_jac = h_misc + 4;    // 4 Jacobi norms, then its status word
     SyncOnUnwind unwind_sync{s};
 
     Result R{};
@@ -538,14 +560,21 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
             for (int j = L; j < ne; ++j) info.matvecs_filter += deg[j];
         }
         CHASE_HIP(hipEventRecord(ev[1], s));
-        qr_robust(V, B1, T, ne, N, L, ne, G, Bq, cwork, gpart, dinfo,
-                  reinterpret_cast<int *>(h_misc), o.seed, qr_salt, s);
+        int *h_qr = reinterpret_cast<int *>(h_misc);
+        qr_launch(V, B1, T, ne, N, L, ne, G, Bq, cwork, gpart, dinfo, h_qr, ev[5], s);
         CHASE_HIP(hipEventRecord(ev[2], s));
         Z *Q = V + L;
+        // The product W = H Q runs while the host checks the QR.
         gemm_other(Q, ne, W + L, ne, n);
+        if (qr_finish(V, B1, T, ne, N, L, ne, G, Bq, cwork, gpart, dinfo, h_qr, ev[5], o.seed,
+                      qr_salt, s)) {
+            CHASE_HIP(hipEventRecord(ev[2], s));
+            gemm_other(Q, ne, W + L, ne, n);
+        }
         gram(Q, ne, W + L, ne, N, n, n, G, n, gpart, s);
         hermitise(G, n, s);
-        jacobi_eig(G, n, theta, Y, jwork, h_jac, s, o.graphs ? &jgraphs : nullptr);
+        int *h_jst = reinterpret_cast<int *>(h_jac + 4);   // read after the sync below
+        jacobi_eig(G, n, theta, Y, jwork, h_jac, s, o.graphs ? &jgraphs : nullptr, h_jst);
         tsmm(Q, ne, Y, n, N, n, n, 1.0, nullptr, 0, 0.0, B1 + L, ne, s);
         CHASE_HIP(hipEventRecord(ev[3], s));
         tsmm(W + L, ne, Y, n, N, n, n, 1.0, nullptr, 0, 0.0, T + L, ne, s);
@@ -555,6 +584,7 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
         CHASE_HIP(hipMemcpyAsync(h_th, theta, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipMemcpyAsync(h_res, resid, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         CHASE_HIP(hipStreamSynchronize(s));
+        jacobi_check_status(n, *h_jst);
         {
             const double nd = n, Ld = L;
             info.qr_flops += 32.0 * Nd * Ld * nd + 48.0 * Nd * nd * nd;
@@ -662,8 +692,8 @@ Result solve(const Problem &p, void *dwork, Z *dV, int64_t ldv, hipStream_t s) {
                                      hipMemcpyHostToDevice, s));
             permute_cols(V + L, ne, B1 + L, ne, N, ne - L, perm, s);
             copy_block(B1 + L, ne, V + L, ne, N, ne - L, s);
-            // hperm is read by the copy above before the next host write
-            CHASE_HIP(hipStreamSynchronize(s));
+            // hperm is next written after the next iteration's stream
+            // synchronisation, by which time this copy has read it.
         }
     }
     info.alpha = alpha;
