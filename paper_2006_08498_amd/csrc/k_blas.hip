@@ -19,25 +19,44 @@ __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
 // part[s] (p x q) = sum over rows of chunk s of conj(A[i, :])^T B[i, :].
 // Workgroup = 4 waves over interleaved 4-row steps of the chunk, one
 // 16 x 16*WN tile of C; the four wave sums are added in LDS in wave order.
-// herm (A = B, a Hermitian result): tiles wholly below the diagonal are
-// skipped; the partial sums fill them from their mirror images.
+// Each wave keeps kGramDepth steps' operands in flight (registers), so the
+// loads of later steps overlap the products of the current one.
+// herm (A = B, p = q, a Hermitian result): only the tiles that reach the
+// diagonal or above are launched (active(jb) = min(pb, (jb + 1) WN) row
+// tiles in column tile jb); the partial sums fill the rest from their
+// mirror images.
+constexpr int kGramDepth = 4;
+
 template <int WN>
 __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
                                               int64_t lda,
                                               const Z *__restrict__ B,
                                               int64_t ldb, int N, int p, int q,
-                                              int pb, int qb, int chunk,
-                                              Z *__restrict__ part, int herm) {
+                                              int pb, int qb, int tiles, int chunk,
+                                              int nchunks, Z *__restrict__ part, int herm) {
     __shared__ double red[3][64 * 8 * WN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, qq = lane >> 4;
-    int t = blockIdx.x;
-    const int ib = t % pb;
-    t /= pb;
-    const int jb = t % qb;
-    const int s = t / qb;
+    // XCD-aware order: workgroup b runs on XCD b % 8, and every tile of
+    // chunk s is placed on XCD s % 8, so the chunk's rows come from HBM
+    // once and are re-read from that XCD's L2.
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int tile = slot % tiles, s = xcd + 8 * (slot / tiles);
+    if (s >= nchunks) return;   // padding of the chunk count to a multiple of 8
+    int ib, jb;
+    if (!herm) {
+        ib = tile % pb;
+        jb = tile / pb;
+    } else {
+        jb = 0;
+        int rest = tile;
+        while (rest >= min(pb, (jb + 1) * WN)) {
+            rest -= min(pb, (jb + 1) * WN);
+            ++jb;
+        }
+        ib = rest;
+    }
     const int p0 = ib * 16, q0 = jb * 16 * WN;
-    if (herm && q0 + 16 * WN <= p0) return;   // uniform: whole workgroup
     const int kbeg = s * chunk, kend = min(N, kbeg + chunk);
     const int acol = min(p0 + r, p - 1);
     int bcol[WN];
@@ -49,20 +68,34 @@ __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
         cr[c] = v4d{0, 0, 0, 0};
         ci[c] = v4d{0, 0, 0, 0};
     }
-    for (int k = kbeg + 4 * wave; k < kend; k += 16) {
+    // Step operands: rows past the chunk read row kbeg and count as zero.
+    Z abuf[kGramDepth], bbuf[kGramDepth][WN];
+    bool okb[kGramDepth];
+    auto load = [&](int k, int d) {
         const int row = k + qq;
-        const bool ok = row < kend;
-        const int rr = ok ? row : kbeg;
-        Z a = A[(int64_t)rr * lda + acol];
-        if (!ok) a = Z{0.0, 0.0};
-        const double nay = -a.y;
+        okb[d] = row < kend;
+        const int64_t rr = okb[d] ? row : kbeg;
+        abuf[d] = A[rr * lda + acol];
 #pragma unroll
-        for (int c = 0; c < WN; ++c) {
-            const Z bv = B[(int64_t)rr * ldb + bcol[c]];
-            cr[c] = mfma64(a.x, bv.x, cr[c]);
-            ci[c] = mfma64(a.x, bv.y, ci[c]);
-            cr[c] = mfma64(a.y, bv.y, cr[c]);
-            ci[c] = mfma64(nay, bv.x, ci[c]);
+        for (int c = 0; c < WN; ++c) bbuf[d][c] = B[rr * ldb + bcol[c]];
+    };
+    const int k0 = kbeg + 4 * wave;
+#pragma unroll
+    for (int d = 0; d < kGramDepth; ++d) load(k0 + 16 * d, d);
+    for (int k = k0; k < kend; k += 16 * kGramDepth) {
+#pragma unroll
+        for (int d = 0; d < kGramDepth; ++d) {
+            const Z a = okb[d] ? abuf[d] : Z{0.0, 0.0};
+            const double nay = -a.y;
+#pragma unroll
+            for (int c = 0; c < WN; ++c) {
+                const Z bv = bbuf[d][c];
+                cr[c] = mfma64(a.x, bv.x, cr[c]);
+                ci[c] = mfma64(a.x, bv.y, ci[c]);
+                cr[c] = mfma64(a.y, bv.y, cr[c]);
+                ci[c] = mfma64(nay, bv.x, ci[c]);
+            }
+            load(k + 16 * (d + kGramDepth), d);
         }
     }
     // Fixed-order sum of the four waves' tiles.
@@ -99,45 +132,73 @@ __global__ __launch_bounds__(256) void k_gram(const Z *__restrict__ A,
     }
 }
 
-// C = sum of the partials in a fixed order.  herm: only the entries on and
-// above the diagonal are summed; each sets its mirror to the conjugate and
-// a diagonal entry is made real, so C is Hermitian to the last bit.
-__global__ void k_sum_parts(const Z *__restrict__ part, int nparts, int p,
-                            int q, Z *__restrict__ C, int64_t ldc, int herm) {
+// C = sum of the partials in a fixed order: a workgroup owns 64 entries,
+// wave w sums partials w, w + 4, ... and the four sums are added in wave
+// order.  herm: only the entries on and above the diagonal are summed;
+// each sets its mirror to the conjugate and a diagonal entry is made real,
+// so C is Hermitian to the last bit.
+__global__ __launch_bounds__(256) void k_sum_parts(const Z *__restrict__ part, int nparts,
+                                                   int p, int q, Z *__restrict__ C,
+                                                   int64_t ldc, int herm) {
+    __shared__ Z red[3][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t total = (int64_t)p * q;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / q, j = t - i * q;
-        if (herm && i > j) continue;
-        double sr = 0.0, si = 0.0;
-        for (int s = 0; s < nparts; ++s) {
-            const Z v = part[(int64_t)s * total + t];
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t tc = t < total ? t : 0;
+    const int64_t i = tc / q, j = tc - i * q;
+    const bool skip = herm && i > j;   // uniform per entry across the waves
+    double sr = 0.0, si = 0.0;
+    if (!skip) {
+        int sidx = wave;
+        for (; sidx + 12 < nparts; sidx += 16) {
+            Z v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)(sidx + 4 * u) * total + tc];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sr += v[u].x;
+                si += v[u].y;
+            }
+        }
+        for (; sidx < nparts; sidx += 4) {
+            const Z v = part[(int64_t)sidx * total + tc];
             sr += v.x;
             si += v.y;
         }
-        if (!herm) {
-            C[i * ldc + j] = Z{sr, si};
-        } else if (i == j) {
-            C[i * ldc + j] = Z{sr, 0.0};
-        } else {
-            C[i * ldc + j] = Z{sr, si};
-            C[j * ldc + i] = Z{sr, -si};
-        }
+    }
+    if (wave > 0) red[wave - 1][lane] = Z{sr, si};
+    __syncthreads();
+    if (wave != 0 || t >= total || skip) return;
+    for (int w = 0; w < 3; ++w) {
+        sr += red[w][lane].x;
+        si += red[w][lane].y;
+    }
+    if (!herm) {
+        C[i * ldc + j] = Z{sr, si};
+    } else if (i == j) {
+        C[i * ldc + j] = Z{sr, 0.0};
+    } else {
+        C[i * ldc + j] = Z{sr, si};
+        C[j * ldc + i] = Z{sr, -si};
     }
 }
 
 struct GramPlan {
-    int wn, pb, qb, chunks, chunk;
+    int wn, pb, qb, tiles, chunks, chunk;
 };
 
-GramPlan gram_plan(int64_t N, int p, int q) {
+GramPlan gram_plan(int64_t N, int p, int q, bool herm) {
     GramPlan g{};
     const int nb = (q + 15) / 16;
     g.qb = (nb + 3) / 4;   // at most 4 tiles per wave (LDS: 48 KiB)
     g.wn = (nb + g.qb - 1) / g.qb;
     g.pb = (p + 15) / 16;
-    const int64_t tiles = (int64_t)g.pb * g.qb;
-    int64_t want = (1024 + tiles - 1) / tiles;
+    g.tiles = g.pb * g.qb;
+    if (herm) {
+        g.tiles = 0;
+        for (int jb = 0; jb < g.qb; ++jb) g.tiles += std::min(g.pb, (jb + 1) * g.wn);
+    }
+    int64_t want = (1024 + g.tiles - 1) / g.tiles;
     int64_t maxc = (N + 255) / 256;
     g.chunks = (int)std::max<int64_t>(1, std::min(want, maxc));
     int64_t ch = (N + g.chunks - 1) / g.chunks;
@@ -150,9 +211,9 @@ GramPlan gram_plan(int64_t N, int p, int q) {
 template <int WN>
 void launch_gram(const GramPlan &g, const Z *A, int64_t lda, const Z *B,
                  int64_t ldb, int N, int p, int q, Z *part, int herm, hipStream_t s) {
-    const int blocks = g.pb * g.qb * g.chunks;
+    const int blocks = g.tiles * ((g.chunks + 7) / 8 * 8);
     hipLaunchKernelGGL(k_gram<WN>, dim3(blocks), dim3(256), 0, s, A, lda, B,
-                       ldb, N, p, q, g.pb, g.qb, g.chunk, part, herm);
+                       ldb, N, p, q, g.pb, g.qb, g.tiles, g.chunk, g.chunks, part, herm);
 }
 
 // ------------------------------------------------------------------ tsmm
@@ -167,7 +228,10 @@ __global__ __launch_bounds__(256) void k_tsmm(
     Z *C, int64_t ldc, int cb, int upper) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, qq = lane >> 4;
-    const int rbk = blockIdx.x / cb, cbk = blockIdx.x % cb;
+    // XCD-aware order: workgroup b runs on XCD b % 8; the column blocks of
+    // row block rbk share XCD rbk % 8, so A's rows are re-read from its L2.
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int rbk = xcd + 8 * (slot / cb), cbk = slot % cb;
     const int row0 = rbk * 64 + wave * 16;
     if (row0 >= N) return;
     const int col0 = cbk * 16 * WN;
@@ -183,20 +247,37 @@ __global__ __launch_bounds__(256) void k_tsmm(
         ci[c] = v4d{0, 0, 0, 0};
     }
     const int kmax = upper ? min(p, col0 + 16 * WN) : p;
-    for (int k = 0; k < kmax; k += 4) {
+    // Step operands, D steps in flight; steps past kmax read
+    // k = 0 and count as zero.
+    constexpr int D = WN <= 4 ? 4 : 2;
+    Z abuf[D], bbuf[D][WN];
+    bool okb[D];
+    auto load = [&](int k, int d) {
         const int kk = k + qq;
-        const bool ok = kk < kmax;
-        const int kc = ok ? kk : 0;
-        Z a = ap[kc];
-        if (!ok) a = Z{0.0, 0.0};
-        const double nay = -a.y;
+        okb[d] = kk < kmax;
+        const int kc = okb[d] ? kk : 0;
+        abuf[d] = ap[kc];
 #pragma unroll
-        for (int c = 0; c < WN; ++c) {
-            const Z bv = B[(int64_t)kc * ldb + bcol[c]];
-            cr[c] = mfma64(a.x, bv.x, cr[c]);
-            ci[c] = mfma64(a.x, bv.y, ci[c]);
-            cr[c] = mfma64(nay, bv.y, cr[c]);
-            ci[c] = mfma64(a.y, bv.x, ci[c]);
+        for (int c = 0; c < WN; ++c) bbuf[d][c] = B[(int64_t)kc * ldb + bcol[c]];
+    };
+    if (kmax > 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(4 * d, d);
+    }
+    for (int k = 0; k < kmax; k += 4 * D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const Z a = okb[d] ? abuf[d] : Z{0.0, 0.0};
+            const double nay = -a.y;
+#pragma unroll
+            for (int c = 0; c < WN; ++c) {
+                const Z bv = bbuf[d][c];
+                cr[c] = mfma64(a.x, bv.x, cr[c]);
+                ci[c] = mfma64(a.x, bv.y, ci[c]);
+                cr[c] = mfma64(nay, bv.y, cr[c]);
+                ci[c] = mfma64(a.y, bv.x, ci[c]);
+            }
+            load(k + 4 * (d + D), d);
         }
     }
 #pragma unroll
@@ -533,8 +614,9 @@ inline int grid_for(int64_t total) {
 }  // namespace
 
 size_t gram_partial_elems(int64_t N, int p, int q) {
-    const GramPlan g = gram_plan(N, p, q);
-    return (size_t)g.chunks * (size_t)p * (size_t)q;
+    int chunks = gram_plan(N, p, q, false).chunks;
+    if (p == q) chunks = std::max(chunks, gram_plan(N, p, q, true).chunks);
+    return (size_t)chunks * (size_t)p * (size_t)q;
 }
 
 void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
@@ -543,7 +625,7 @@ void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
     if (herm && (A != B || lda != ldb || p != q))
         throw Error(7, "gram: a Hermitian product needs A = B");
     const int N = (int)N64;
-    const GramPlan g = gram_plan(N64, p, q);
+    const GramPlan g = gram_plan(N64, p, q, herm);
     switch (g.wn) {
 #define CASE(w) case w: launch_gram<w>(g, A, lda, B, ldb, N, p, q, part, herm ? 1 : 0, s); break;
         CASE(1) CASE(2) CASE(3) CASE(4)
@@ -551,7 +633,7 @@ void gram(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
         default: throw Error(7, "gram: bad tile width");
     }
     check_launch("k_gram");
-    hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((int64_t)p * q)), dim3(256),
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(((int64_t)p * q + 63) / 64)), dim3(256),
                        0, s, part, g.chunks, p, q, C, ldc, herm ? 1 : 0);
     check_launch("k_sum_parts");
 }
@@ -565,7 +647,7 @@ void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
     const int cb = (nb + 7) / 8;
     const int wn = (nb + cb - 1) / cb;
     const int rb = (N + 63) / 64;
-    const dim3 grid(rb * cb);
+    const dim3 grid((rb + 7) / 8 * 8 * cb);   // row blocks past N return at once
     switch (wn) {
 #define CASE(w)                                                                \
     case w:                                                                    \

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace chase {
@@ -34,20 +35,22 @@ __device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s};
 // row-major) with L the lower Cholesky factor of W = D G D + shift I and
 // D = diag(G)^{-1/2}, so that V <- V B orthonormalises.  *info = 0, or
 // j + 1 for the first non-positive (or non-finite) pivot j (then B is not
-// written).
+// complete).
 //
 // Blocked in 16 x 16 complex blocks (nt = ceil(n / 16) per side; W is
 // padded with the identity to 16 nt, which leaves L and L^{-1} padded with
-// the identity), right-looking:
-//  * step k: the diagonal block W_kk is factored in LDS by one wave and its
-//    inverse formed by column-parallel forward substitution (no workgroup
-//    barrier inside; three per block column in all); the panel L_ik = W_ik L_kk^{-H} (i > k) and the trailing
-//    update W_ij -= L_ik L_jk^H (k < j <= i) are 16 x 16 x 16 complex
-//    products on FP64 MFMA, one block per wave at a time;
-//  * then X = L^{-1} by block rows: X_ii = L_ii^{-1} and, for k < i,
-//    X_ik = -L_ii^{-1} sum_{j=k}^{i-1} L_ij X_jk (the sum's result feeds the
-//    second product straight from the accumulator registers).
-// W, X, the diagonal blocks' inverses and D live in `work`
+// the identity), right-looking with a look-ahead of one diagonal block.
+// Step k, after the inverse of the diagonal block L_kk is known:
+//  * phase P: the panel L_ik = W_ik L_kk^{-H} (i > k), staged in LDS as
+//    well, and X_kk = L_kk^{-1} (X = L^{-1});
+//  * phase T: wave 0 updates W_{k+1,k+1} and factors and inverts it
+//    (diag_factor) while the other waves do block row k of X,
+//    X_kj = -L_kk^{-1} sum_{m=j}^{k-1} L_km X_mj (j < k, whose operands were
+//    final at earlier steps), and the rest of the trailing update
+//    W_ij -= L_ik L_jk^H (k < j <= i).
+// Block products are 16 x 16 x 16 complex on FP64 MFMA.  Every X block is
+// written to B (conjugate transpose, scaled) by the wave that forms it.
+// Two workgroup barriers per step.  W, X and D live in `work`
 // (chol_work_elems(n)), L2-resident at these orders.
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -72,10 +75,12 @@ __device__ __forceinline__ void zblock_mac(v4d &cr, v4d &ci, FA a_at, FB b_at) {
     }
 }
 
-// 8 waves (2 per SIMD): room is left on the CU for other kernels (a
-// 16-wave workgroup of this register size needs a whole idle CU, which a
-// busy GPU rarely has).
+// 8 waves (2 per SIMD): room is left on the CU for other kernels.
 constexpr int kCholThreads = 512;
+constexpr int kCholWaves = kCholThreads / 64;
+// Panel blocks staged in LDS (n <= 16 (kPanelLds + 1)); beyond, the
+// trailing update reads them from W.
+constexpr int kPanelLds = 32;
 
 size_t chol_np(int n) { return (size_t)(n + 15) / 16 * 16; }
 
@@ -86,22 +91,107 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Calls f(integral_constant<int, I>) for I = B .. E-1 (compile-time indices,
+// as the DPP lane selects below need).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// The double held by lane M of each row of 16 lanes, to every lane of that
+// row (DPP row_newbcast).
+template <int M>
+__device__ __forceinline__ double row_bcast(double v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + M, 0xf, 0xf, false);   // one 64-bit DPP move
+}
+
+// One wave: the 16 x 16 diagonal block in Ls (lower part; the wave's own
+// writes, ordered before the call) -> L^{-1} (its Cholesky factor's
+// inverse) in linv.  Lane i (of every row of
+// 16 lanes: the four rows hold the same data) keeps row i in registers;
+// column j's pivot and entries reach the other lanes by DPP broadcasts, so
+// no LDS round trip per column and no workgroup barrier falls inside.  Then
+// L goes to Ls and lane c forms column c of L^{-1} by forward substitution.
+// Returns j + 1 for a non-positive or non-finite pivot j (linv then
+// unwritten), else 0.
+__device__ __forceinline__ int diag_factor(Z (*Ls)[17], Z (*linv)[17]) {
+    const int lane = threadIdx.x & 63, i = lane & 15;
+    Z a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = m <= i ? Ls[i][m] : Z{0.0, 0.0};
+    double il[16];
+    int bad = 0;
+    static_for<0, 16>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (bad) return;
+        const double piv = row_bcast<j>(a[j].x);   // the same in every lane
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            bad = j + 1;
+            return;
+        }
+        const double rl = rsqrt(piv);
+        il[j] = rl;
+        if (i > j) a[j] = zscale(a[j], rl);
+        else if (i == j) a[j] = Z{piv * rl, 0.0};
+        // a[i][m] -= L_ij conj(L_mj), m > j (entries above the diagonal are
+        // updated too and never read).
+        static_for<j + 1, 16>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const Z lm{row_bcast<m>(a[j].x), row_bcast<m>(a[j].y)};
+            // a[m] -= a[j] conj(lm), four fused multiply-adds
+            a[m].x = fma(-a[j].x, lm.x, fma(-a[j].y, lm.y, a[m].x));
+            a[m].y = fma(a[j].x, lm.y, fma(-a[j].y, lm.x, a[m].y));
+        });
+    });
+    if (bad) return bad;
+    // L to LDS by rows, then column c of L^{-1}, x_r = (delta_rc -
+    // sum_{m<r} L_rm x_m) / L_rr, right-looking (x_r is final at step r and
+    // is then subtracted from the rows below it at once, which keeps the
+    // dependent chain at 16 steps; each x_r's terms are still added in the
+    // order m = 0, 1, ...), reading L back as broadcasts.
+    if (lane < 16) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) Ls[i][m] = a[m];
+    }
+    wave_sync();
+    Z x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = Z{i == r ? 1.0 : 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        x[j] = zscale(x[j], il[j]);
+#pragma unroll
+        for (int r = j + 1; r < 16; ++r) {
+            const Z l = Ls[r][j];   // x[r] -= l x[j]
+            x[r].x = fma(l.y, x[j].y, fma(-l.x, x[j].x, x[r].x));
+            x[r].y = fma(-l.y, x[j].x, fma(-l.x, x[j].y, x[r].y));
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) linv[r][i] = x[r];
+    }
+    return 0;
+}
+
 __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restrict__ G, int n,
                                                                double shift, Z *__restrict__ B,
                                                                Z *__restrict__ work,
                                                                int *info) {
-    __shared__ Z dblk[16][17];   // diagonal block being factored (lower)
-    __shared__ Z linv[16][17];   // its inverse
-    __shared__ double ldg[16];   // its diagonal
+    __shared__ Z linv[2][16][17];          // L_kk^{-1}, by step parity
+    __shared__ Z Lp[kPanelLds][16][17];    // the panel L_ik, i = k + 1 + index
+    __shared__ Z Ls[16][17];               // the diagonal block's factor
     __shared__ int bad;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int nwaves = kCholThreads / 64;
     const int r = lane & 15, q = lane >> 4;
     const int nt = (n + 15) / 16, np = 16 * nt;
+    const bool lds_panel = nt - 1 <= kPanelLds;
     Z *W = work;                                  // np x np, row-major
     Z *X = W + (size_t)np * np;                   // np x np: L^{-1}
-    Z *Li = X + (size_t)np * np;                  // nt blocks of 16 x 16
-    double *dsc = reinterpret_cast<double *>(Li + (size_t)nt * 256);   // np
+    double *dsc = reinterpret_cast<double *>(X + (size_t)np * np);   // np
 
     if (t == 0) bad = 0x7fffffff;
     __syncthreads();
@@ -115,60 +205,208 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
         if (t == 0) *info = bad;
         return;
     }
-    // W = D G D + shift I, padded with the identity.
-    for (int64_t e = t; e < (int64_t)np * np; e += kCholThreads) {
-        const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
-        Z v{i == j ? 1.0 : 0.0, 0.0};
-        if (i < n && j < n) {
-            v = zscale(G[(int64_t)i * n + j], dsc[i] * dsc[j]);
-            if (i == j) v = Z{v.x + shift, 0.0};
+    // W = D G D + shift I, padded with the identity (the lower triangle is
+    // all that is read); B below its diagonal blocks is zero.
+    // (Eight entries per thread in flight: the loads are issued together.)
+    for (int64_t e0 = t; e0 < (int64_t)np * np; e0 += 8 * kCholThreads) {
+        Z g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + (int64_t)u * kCholThreads;
+            const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
+            g[u] = (e < (int64_t)np * np && j <= i && i < n) ? G[(int64_t)i * n + j]
+                                                              : Z{0.0, 0.0};
         }
-        W[e] = v;
-        X[e] = Z{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + (int64_t)u * kCholThreads;
+            const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
+            if (e >= (int64_t)np * np || j > i) continue;
+            Z v{i == j ? 1.0 : 0.0, 0.0};
+            if (i < n) {
+                v = zscale(g[u], dsc[i] * dsc[j]);
+                if (i == j) v = Z{v.x + shift, 0.0};
+            }
+            W[e] = v;
+        }
+    }
+    for (int64_t e = t; e < (int64_t)n * n; e += kCholThreads) {
+        const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
+        if (i / 16 < j / 16) B[e] = Z{0.0, 0.0};
     }
     __syncthreads();
 
+    // Block (i, k) of X, in accumulator layout, to X and to B = D X^H.
+    auto put_x = [&](int i, int k, const v4d &xr, const v4d &xi) {
+        Z *Xik = X + (int64_t)16 * i * np + 16 * k;
+        const int brow = 16 * k + r;
+        const double sc = brow < n ? dsc[brow] : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            Xik[(int64_t)(q + 4 * v) * np + r] = Z{xr[v], xi[v]};
+            const int bcol = 16 * i + q + 4 * v;
+            if (brow < n && bcol < n)
+                B[(int64_t)brow * n + bcol] = Z{xr[v] * sc, -xi[v] * sc};
+        }
+    };
+
+    if (wave == 0) {
+        for (int e = lane; e < 256; e += 64) Ls[e >> 4][e & 15] = W[(e >> 4) * np + (e & 15)];
+        wave_sync();
+        const int b0 = diag_factor(Ls, linv[0]);
+        if (b0 && lane == 0) bad = b0;
+    }
+    __syncthreads();
+    if (bad != 0x7fffffff) {
+        if (t == 0) *info = bad;
+        return;
+    }
+
     for (int k = 0; k < nt; ++k) {
         const int64_t kk0 = (int64_t)16 * k;
-        // ---- diagonal block: Cholesky and inverse in LDS by wave 0 alone
-        // (its lanes order their LDS accesses among themselves; the other
-        // waves wait at the barrier below).
+        Z (*li)[17] = linv[k & 1];
+        // ---- phase P: X_kk and the panel L_ik = W_ik L_kk^{-H}, i > k.
+        // Wave 0 also fetches W_{k+1,k+1} (final since the last step) for
+        // its update in phase T.
+        v4d dr{0, 0, 0, 0}, di{0, 0, 0, 0};
+        if (wave == 0 && k + 1 < nt) {
+            const Z *Wii = W + (int64_t)16 * (k + 1) * np + 16 * (k + 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const Z w = Wii[(int64_t)(q + 4 * v) * np + r];
+                dr[v] = w.x;
+                di[v] = w.y;
+            }
+        }
         if (wave == 0) {
-            for (int e = lane; e < 256; e += 64) {
-                const int i = e >> 4, m = e & 15;
-                dblk[i][m] = m <= i ? W[(kk0 + i) * np + kk0 + m] : Z{0.0, 0.0};
+            v4d xr, xi;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                xr[v] = li[q + 4 * v][r].x;
+                xi[v] = li[q + 4 * v][r].y;
             }
-            wave_sync();
-            for (int j = 0; j < 16; ++j) {
-                const double piv = dblk[j][j].x;
-                if (!(piv > 0.0) || !isfinite(piv)) {
-                    if (lane == 0) bad = 16 * k + j + 1;
-                    break;   // uniform across the wave: every lane read the same pivot
-                }
-                const double l = sqrt(piv), il = 1.0 / l;
-                if (lane == 0) ldg[j] = l;
-                if (lane > j && lane < 16) dblk[lane][j] = zscale(dblk[lane][j], il);
-                wave_sync();
-                for (int e = lane; e < 256; e += 64) {
-                    const int i = e >> 4, m = e & 15;
-                    if (m > j && m <= i)
-                        dblk[i][m] = zsub(dblk[i][m], zmul(dblk[i][j], zconj(dblk[m][j])));
-                }
-                wave_sync();
+            put_x(k, k, xr, xi);
+        }
+        for (int i = k + 1 + wave; i < nt; i += kCholWaves) {
+            const Z *Wi = W + (int64_t)16 * i * np + kk0;
+            v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
+            zblock_mac(cr, ci, [&](int s) { return Wi[(int64_t)r * np + 4 * s + q]; },
+                       [&](int s) { return zconj(li[r][4 * s + q]); });
+            Z *Wo = W + (int64_t)16 * i * np + kk0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const Z o{cr[v], ci[v]};
+                Wo[(int64_t)(q + 4 * v) * np + r] = o;
+                if (lds_panel) Lp[i - k - 1][q + 4 * v][r] = o;
             }
-            wave_sync();
-            if (bad == 0x7fffffff) {
-                if (lane < 16) dblk[lane][lane] = Z{ldg[lane], 0.0};
+        }
+        __syncthreads();
+        // ---- phase T
+        if (wave == 0) {
+            if (k + 1 < nt) {
+                // W_{k+1,k+1} -= L_{k+1,k} L_{k+1,k}^H (the panel block from
+                // LDS when staged), into Ls, then its factor.  W_{k+1,k+1}
+                // itself is not read again.
+                const int i = k + 1;
+                if (lds_panel) {
+                    zblock_mac(dr, di,
+                               [&](int s) {
+                                   const Z a = Lp[0][r][4 * s + q];
+                                   return Z{-a.x, -a.y};
+                               },
+                               [&](int s) { return zconj(Lp[0][r][4 * s + q]); });
+                } else {
+                    const Z *Lik = W + (int64_t)16 * i * np + kk0;
+                    zblock_mac(dr, di,
+                               [&](int s) {
+                                   const Z a = Lik[(int64_t)r * np + 4 * s + q];
+                                   return Z{-a.x, -a.y};
+                               },
+                               [&](int s) { return zconj(Lik[(int64_t)r * np + 4 * s + q]); });
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Ls[q + 4 * v][r] = Z{dr[v], di[v]};
                 wave_sync();
-                // Inverse, one column per lane (forward substitution).
-                if (lane < 16) {
-                    const int c = lane;
-                    for (int i = 0; i < 16; ++i) {
-                        Z acc{i == c ? 1.0 : 0.0, 0.0};
-                        for (int m = c; m < i; ++m) acc = zsub(acc, zmul(dblk[i][m], linv[m][c]));
-                        linv[i][c] = i < c ? Z{0.0, 0.0} : zscale(acc, 1.0 / ldg[i]);
+                const int bi = diag_factor(Ls, linv[(k + 1) & 1]);
+                if (bi && lane == 0) bad = 16 * (k + 1) + bi;
+            }
+        } else {
+            // Jobs: X row k (j = 0 .. k-1, the longest sums first), then the
+            // trailing tiles other than (k+1, k+1); round-robin over waves
+            // 1 .. kCholWaves - 1.
+            const int m = nt - k - 1;
+            const int tiles = m * (m + 1) / 2;
+            const int jobs = k + tiles;
+            for (int u = wave - 1; u < jobs; u += kCholWaves - 1) {
+                if (u < k) {
+                    const int j = u;
+                    v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
+                    const Z *Lk = W + kk0 * np;
+                    Z la[4], xa[4];
+                    auto load = [&](int mm, Z *lo, Z *xo) {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            lo[s] = Lk[(int64_t)r * np + 16 * mm + 4 * s + q];
+                            xo[s] = X[(int64_t)(16 * mm + 4 * s + q) * np + 16 * j + r];
+                        }
+                    };
+                    load(j, la, xa);
+                    for (int mm = j; mm < k; ++mm) {
+                        Z lb[4], xb[4];
+                        load(min(mm + 1, k - 1), lb, xb);   // next operands in flight
+                        zblock_mac(cr, ci, [&](int s) { return la[s]; },
+                                   [&](int s) { return xa[s]; });
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            la[s] = lb[s];
+                            xa[s] = xb[s];
+                        }
                     }
+                    v4d xr{0, 0, 0, 0}, xi{0, 0, 0, 0};
+                    zblock_mac(xr, xi,
+                               [&](int s) {
+                                   const Z a = li[r][4 * s + q];
+                                   return Z{-a.x, -a.y};
+                               },
+                               [&](int s) { return Z{cr[s], ci[s]}; });
+                    put_x(k, j, xr, xi);
+                    continue;
                 }
+                // Trailing tile number tt (row-major over k < j <= i),
+                // skipping (k+1, k+1), which is tile 0.
+                const int tt = u - k + 1;
+                if (tt >= tiles) continue;
+                int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+                while (ii * (ii + 1) / 2 > tt) --ii;
+                while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
+                const int i = k + 1 + ii, j = k + 1 + tt - ii * (ii + 1) / 2;
+                Z *Wij = W + (int64_t)16 * i * np + 16 * j;
+                v4d cr, ci;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const Z w = Wij[(int64_t)(q + 4 * v) * np + r];
+                    cr[v] = w.x;
+                    ci[v] = w.y;
+                }
+                if (lds_panel) {
+                    zblock_mac(cr, ci,
+                               [&](int s) {
+                                   const Z a = Lp[i - k - 1][r][4 * s + q];
+                                   return Z{-a.x, -a.y};
+                               },
+                               [&](int s) { return zconj(Lp[j - k - 1][r][4 * s + q]); });
+                } else {
+                    const Z *Lik = W + (int64_t)16 * i * np + kk0;
+                    const Z *Ljk = W + (int64_t)16 * j * np + kk0;
+                    zblock_mac(cr, ci,
+                               [&](int s) {
+                                   const Z a = Lik[(int64_t)r * np + 4 * s + q];
+                                   return Z{-a.x, -a.y};
+                               },
+                               [&](int s) { return zconj(Ljk[(int64_t)r * np + 4 * s + q]); });
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Wij[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
             }
         }
         __syncthreads();
@@ -176,81 +414,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
             if (t == 0) *info = bad;
             return;   // uniform: every thread reads the flag after the barrier
         }
-        if (t < 256) {
-            const int i = t >> 4, m = t & 15;
-            Li[(int64_t)k * 256 + i * 16 + m] = linv[i][m];
-            X[(kk0 + i) * np + kk0 + m] = linv[i][m];
-        }
-        // ---- panel: L_ik = W_ik L_kk^{-H}, i > k
-        for (int i = k + 1 + wave; i < nt; i += nwaves) {
-            const Z *Wi = W + (int64_t)16 * i * np + kk0;
-            v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
-            zblock_mac(cr, ci, [&](int s) { return Wi[(int64_t)r * np + 4 * s + q]; },
-                       [&](int s) { return zconj(linv[r][4 * s + q]); });
-            Z *Wo = W + (int64_t)16 * i * np + kk0;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Wo[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
-        }
-        __syncthreads();
-        // ---- trailing update: W_ij -= L_ik L_jk^H, k < j <= i
-        const int m = nt - k - 1;
-        const int tiles = m * (m + 1) / 2;
-        for (int tt = wave; tt < tiles; tt += nwaves) {
-            int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-            while (ii * (ii + 1) / 2 > tt) --ii;
-            while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
-            const int jj = tt - ii * (ii + 1) / 2;
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            Z *Wij = W + (int64_t)16 * i * np + 16 * j;
-            const Z *Lik = W + (int64_t)16 * i * np + kk0;
-            const Z *Ljk = W + (int64_t)16 * j * np + kk0;
-            v4d cr, ci;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const Z w = Wij[(int64_t)(q + 4 * v) * np + r];
-                cr[v] = w.x;
-                ci[v] = w.y;
-            }
-            zblock_mac(cr, ci,
-                       [&](int s) {
-                           const Z a = Lik[(int64_t)r * np + 4 * s + q];
-                           return Z{-a.x, -a.y};
-                       },
-                       [&](int s) { return zconj(Ljk[(int64_t)r * np + 4 * s + q]); });
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Wij[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
-        }
-        __syncthreads();
-    }
-
-    // ---- X = L^{-1} by block rows
-    for (int i = 1; i < nt; ++i) {
-        const Z *Lii = Li + (int64_t)i * 256;
-        for (int k = wave; k < i; k += nwaves) {
-            v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
-            for (int j = k; j < i; ++j) {
-                const Z *Lij = W + (int64_t)16 * i * np + 16 * j;
-                const Z *Xjk = X + (int64_t)16 * j * np + 16 * k;
-                zblock_mac(cr, ci, [&](int s) { return Lij[(int64_t)r * np + 4 * s + q]; },
-                           [&](int s) { return Xjk[(int64_t)(4 * s + q) * np + r]; });
-            }
-            v4d xr{0, 0, 0, 0}, xi{0, 0, 0, 0};
-            zblock_mac(xr, xi,
-                       [&](int s) {
-                           const Z a = Lii[r * 16 + 4 * s + q];
-                           return Z{-a.x, -a.y};
-                       },
-                       [&](int s) { return Z{cr[s], ci[s]}; });
-            Z *Xik = X + (int64_t)16 * i * np + 16 * k;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Xik[(int64_t)(q + 4 * v) * np + r] = Z{xr[v], xi[v]};
-        }
-        __syncthreads();
-    }
-    // ---- B = D X^H (upper triangular), row j, column i
-    for (int64_t e = t; e < (int64_t)n * n; e += kCholThreads) {
-        const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
-        B[e] = i >= j ? zscale(zconj(X[(int64_t)i * np + j]), dsc[j]) : Z{0.0, 0.0};
     }
     if (t == 0) *info = 0;
 }
@@ -263,8 +426,11 @@ __device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
         a = m - 1;
         b = r;
     } else {
-        a = (r + k) % (m - 1);
-        b = (r - k + (m - 1)) % (m - 1);
+        // (r + k) mod (m - 1) and (r - k) mod (m - 1), 0 <= r, k < m - 1.
+        a = r + k;
+        if (a >= m - 1) a -= m - 1;
+        b = r - k;
+        if (b < 0) b += m - 1;
     }
     p = min(a, b);
     q = max(a, b);
@@ -278,6 +444,7 @@ struct Rot {
     Z e;
     double dp, dq;   // resulting diagonal
     bool active;
+    int p, q;        // the pair (mid-size kernel)
 };
 
 __device__ Rot make_rot(const Z *A, int n, int p, int q) {
@@ -543,6 +710,313 @@ __global__ __launch_bounds__(1024) void k_offnorm(const Z *__restrict__ A,
     }
 }
 
+// ------------------------------------------------ Jacobi, mid-size orders
+// For kJacobiLds < n <= kJacobiMid the whole cyclic Jacobi of A runs in one
+// workgroup with A Hermitian-packed in LDS (upper triangle, n (n + 1) / 2
+// entries: 158 KB at n = 140), every sweep and its convergence test in one
+// launch.  The eigenvectors are not formed there: each round's rotations
+// (c, s, e) are recorded, and a second kernel applies them, in order, to
+// the rows of the identity (each row of V is independent: one wave per row,
+// the row in LDS), then writes Y in ascending eigenvalue order.  The
+// rotations and the update formulas are those of k_jacobi_round.
+constexpr int kJacobiMid = 140;
+constexpr int kJacobiMidThreads = 1024;
+constexpr int kRotSweeps = 30;   // capacity of the rotation record, in sweeps
+
+// Work layout (complex elements): [0, 64) the status words and the
+// permutation (int), then 2 per rotation, kRotSweeps (m - 1) h of them.
+constexpr size_t kMidHead = 64;
+size_t jacobi_mid_elems(int n) {
+    const size_t m = (size_t)(n + (n & 1)), h = m / 2;
+    return kMidHead + 2 * (size_t)kRotSweeps * (m - 1) * h;
+}
+
+__device__ __forceinline__ int pk_idx(int x, int y, int n) {   // x <= y
+    return x * (2 * n - x + 1) / 2 + (y - x);
+}
+// Entry (x, y) of the packed Hermitian matrix (no branch: the stored one
+// and a conjugation); rb[x] = pk_idx(x, x, n) - x.
+__device__ __forceinline__ Z pk_get(const Z *P, const int *rb, int x, int y) {
+    Z v = P[rb[min(x, y)] + max(x, y)];
+    if (x > y) v.y = -v.y;
+    return v;
+}
+__device__ __forceinline__ void pk_set(Z *P, const int *rb, int x, int y, Z v) {
+    if (x > y) v.y = -v.y;
+    P[rb[min(x, y)] + max(x, y)] = v;
+}
+// a * b and conj(a) * b
+__device__ __forceinline__ Z zmul_f(Z a, Z b) {
+    return Z{fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ Z zcmul_f(Z a, Z b) {
+    return Z{fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -a.y * b.x)};
+}
+// c x + s y and c x - s y for real c, s
+__device__ __forceinline__ Z zaxpby(double c, Z x, double s, Z y) {
+    return Z{fma(c, x.x, s * y.x), fma(c, x.y, s * y.y)};
+}
+
+// make_rot on the packed matrix (p < q).
+__device__ Rot make_rot_packed(const Z *P, int n, int p, int q) {
+    Rot R{1.0, 0.0, Z{1.0, 0.0}, 0.0, 0.0, false};
+    const double app = P[pk_idx(p, p, n)].x;
+    R.dp = app;
+    if (q >= n) return R;
+    const double aqq = P[pk_idx(q, q, n)].x;
+    const Z apq = P[pk_idx(p, q, n)];
+    const double x = sqrt(apq.x * apq.x + apq.y * apq.y);
+    R.dq = aqq;
+    if (!(x > 1e-300) || x <= 1e-18 * (fabs(app) + fabs(aqq))) return R;
+    R.e = Z{apq.x / x, -apq.y / x};
+    const double tau = (aqq - app) / (2.0 * x);
+    double t;
+    if (fabs(tau) > 1e150) t = 0.5 / tau;
+    else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    R.c = 1.0 / sqrt(1.0 + t * t);
+    R.s = t * R.c;
+    R.dp = app - t * x;
+    R.dq = aqq + t * x;
+    R.active = true;
+    return R;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(kJacobiMidThreads) void k_jacobi_mid(const Z *__restrict__ A0,
+                                                                  int n, int max_sweeps,
+                                                                  double *__restrict__ w,
+                                                                  Z *__restrict__ work) {
+    __shared__ Z P[kJacobiMid * (kJacobiMid + 1) / 2];
+    __shared__ Rot rot[kJacobiMid / 2];
+    __shared__ int rb[kJacobiMid];
+    __shared__ double red[2][kJacobiMidThreads / 64];
+    __shared__ int decide;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nw = kJacobiMidThreads / 64;
+    const int m = n + (n & 1), h = m / 2;
+    int *hdr = reinterpret_cast<int *>(work);   // [0] status, [1] rounds recorded
+    int *perm = hdr + 16;
+    Z *rec = work + kMidHead;
+    for (int x = t; x < n; x += kJacobiMidThreads) rb[x] = pk_idx(x, x, n) - x;
+    for (int e = t; e < n * (n + 1) / 2; e += kJacobiMidThreads) {
+        // e -> (x, y), x <= y, row-major over the upper triangle
+        int x = (int)((2.0 * n + 1.0 - sqrt((2.0 * n + 1.0) * (2.0 * n + 1.0) - 8.0 * e)) * 0.5);
+        while (x > 0 && pk_idx(x, x, n) > e) --x;
+        while (x + 1 < n && pk_idx(x + 1, x + 1, n) <= e) ++x;
+        const int y = x + (e - pk_idx(x, x, n));
+        P[e] = A0[(int64_t)x * n + y];
+    }
+    __syncthreads();
+    double prev = 1e300;
+    int result = -1, rounds = 0;
+    // Blocks ka <= kb, enumerated folded over hf = h rounded up to even:
+    // rows ka and hf - 1 - ka together hold hf + 1 of them (those with
+    // kb = h, present only when h is odd, are skipped).
+    const int hf = h + (h & 1);
+    const int nblk = hf / 2 * (hf + 1);
+    // This thread's blocks (the same every round): at most kMidBlk.
+    constexpr int kMidBlk = (kJacobiMid / 2 / 2 * (kJacobiMid / 2 + 1) + kJacobiMidThreads - 1) /
+                            kJacobiMidThreads;
+    int bka[kMidBlk], bkb[kMidBlk];
+#pragma unroll
+    for (int u = 0; u < kMidBlk; ++u) {
+        const int e = t + u * kJacobiMidThreads;
+        bka[u] = bkb[u] = -1;
+        if (e >= nblk) continue;
+        const int pr = e / (hf + 1), o = e - pr * (hf + 1);
+        int ka, kb;
+        if (o < hf - pr) {
+            ka = pr;
+            kb = pr + o;
+        } else {
+            ka = hf - 1 - pr;
+            kb = ka + (o - (hf - pr));
+        }
+        if (kb >= h) continue;
+        bka[u] = ka;
+        bkb[u] = kb;
+    }
+    for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+        for (int round = 0; round < m - 1; ++round, ++rounds) {
+            for (int k = t; k < h; k += kJacobiMidThreads) {
+                int p, q;
+                rr_pair(m, round, k, p, q);
+                Rot R = make_rot_packed(P, n, p, q);
+                R.p = p;
+                R.q = q;
+                rot[k] = R;
+                Z *o = rec + 2 * ((int64_t)rounds * h + k);
+                o[0] = Z{R.c, R.s};
+                o[1] = R.e;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kMidBlk; ++u) {
+                const int ka = bka[u], kb = bkb[u];
+                if (ka < 0) continue;
+                const Rot Ra = rot[ka], Rb = rot[kb];
+                const int pa = Ra.p, qa = Ra.q, pb = Rb.p, qb = Rb.q;
+                const bool qa_ok = qa < n, qb_ok = qb < n;
+                if (ka == kb) {
+                    P[rb[pa] + pa] = Z{Ra.dp, 0.0};
+                    if (qa_ok) {
+                        P[rb[qa] + qa] = Z{Ra.dq, 0.0};
+                        if (Ra.active) P[rb[pa] + qa] = Z{0.0, 0.0};
+                    }
+                    continue;
+                }
+                // The update of k_jacobi_round, A' = J_a^H M J_b, written with
+                // J = [[c, s], [-s e, c e]] so that each 2 x 2 factor costs two
+                // complex products and four real-scaled sums.
+                const Z zero{0.0, 0.0};
+                const Z m00 = pk_get(P, rb, pa, pb);
+                const Z m01 = qb_ok ? pk_get(P, rb, pa, qb) : zero;
+                const Z m10 = qa_ok ? pk_get(P, rb, qa, pb) : zero;
+                const Z m11 = (qa_ok && qb_ok) ? pk_get(P, rb, qa, qb) : zero;
+                const Z u0 = zmul_f(Rb.e, m01), u1 = zmul_f(Rb.e, m11);
+                const Z t00 = zaxpby(Rb.c, m00, -Rb.s, u0), t01 = zaxpby(Rb.s, m00, Rb.c, u0);
+                const Z t10 = zaxpby(Rb.c, m10, -Rb.s, u1), t11 = zaxpby(Rb.s, m10, Rb.c, u1);
+                const Z v0 = zcmul_f(Ra.e, t10), v1 = zcmul_f(Ra.e, t11);
+                pk_set(P, rb, pa, pb, zaxpby(Ra.c, t00, -Ra.s, v0));
+                if (qb_ok) pk_set(P, rb, pa, qb, zaxpby(Ra.c, t01, -Ra.s, v1));
+                if (qa_ok) pk_set(P, rb, qa, pb, zaxpby(Ra.s, t00, Ra.c, v0));
+                if (qa_ok && qb_ok) pk_set(P, rb, qa, qb, zaxpby(Ra.s, t01, Ra.c, v1));
+            }
+            __syncthreads();
+        }
+        // Off-diagonal and total Frobenius norms (each stored off-diagonal
+        // entry stands for two).
+        double off = 0.0, tot = 0.0;
+        for (int e = t; e < n * (n + 1) / 2; e += kJacobiMidThreads) {
+            int x = (int)((2.0 * n + 1.0 - sqrt((2.0 * n + 1.0) * (2.0 * n + 1.0) - 8.0 * e)) * 0.5);
+            while (x > 0 && pk_idx(x, x, n) > e) --x;
+            while (x + 1 < n && pk_idx(x + 1, x + 1, n) <= e) ++x;
+            const Z v = P[e];
+            const double mm = v.x * v.x + v.y * v.y;
+            if (e == pk_idx(x, x, n)) {
+                tot += mm;
+            } else {
+                off += 2.0 * mm;
+                tot += 2.0 * mm;
+            }
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        if (lane == 0) {
+            red[0][wave] = off;
+            red[1][wave] = tot;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double so = 0.0, st = 0.0;
+            for (int i = 0; i < nw; ++i) {
+                so += red[0][i];
+                st += red[1][i];
+            }
+            const double o = sqrt(so), tt = sqrt(st);
+            int d = 0;   // 0 continue, 1 converged, 2 non-finite
+            if (!isfinite(o)) d = 2;
+            else if (o <= 1e-15 * tt || (o <= 1e-12 * tt && o >= 0.5 * prev)) d = 1;
+            prev = o;
+            decide = d;
+        }
+        __syncthreads();
+        const int d = decide;
+        __syncthreads();   // decide is rewritten after the next sweep
+        if (d == 2) {
+            result = -2;
+            break;
+        }
+        if (d == 1) {
+            result = sweep + 1;
+            break;
+        }
+    }
+    if (n == 1) result = 0;
+    for (int j = t; j < n; j += kJacobiMidThreads) {
+        const double dj = P[pk_idx(j, j, n)].x;
+        int rank = 0;
+        for (int i = 0; i < n; ++i) {
+            const double di = P[pk_idx(i, i, n)].x;
+            rank += (di < dj) || (di == dj && i < j);
+        }
+        w[rank] = dj;
+        perm[j] = rank;
+    }
+    if (t == 0) {
+        hdr[0] = result;
+        hdr[1] = rounds;
+    }
+}
+
+// Y[i, perm[j]] = V[i, j], V = the product of the recorded rotations
+// applied to the identity: one wave per row i, the row in LDS, pair k of a
+// round handled by lane k % 64.
+constexpr int kRotRowsPerBlock = 4;
+__global__ __launch_bounds__(64 * kRotRowsPerBlock) void k_jacobi_apply_rot(const Z *__restrict__ work,
+                                                                             int n,
+                                                                             Z *__restrict__ Y) {
+    __shared__ Z rows[kRotRowsPerBlock][kJacobiMid + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * kRotRowsPerBlock + wv;
+    if (i >= n) return;   // whole wave; no workgroup barrier below
+    const int m = n + (n & 1), h = m / 2;
+    const int *hdr = reinterpret_cast<const int *>(work);
+    const int *perm = hdr + 16;
+    const Z *rec = work + kMidHead;
+    const int rounds = hdr[1];
+    Z *row = rows[wv];
+    for (int j = lane; j < n; j += 64) row[j] = Z{j == i ? 1.0 : 0.0, 0.0};
+    wave_sync();
+    // Pairs lane and lane + 64 (h <= 70); their rotations for the next round
+    // are loaded while the current one is applied.
+    const bool has0 = lane < h, has1 = lane + 64 < h;
+    Z cs0{1.0, 0.0}, e0{1.0, 0.0}, cs1{1.0, 0.0}, e1{1.0, 0.0};
+    auto fetch = [&](int rd, Z &a0, Z &b0, Z &a1, Z &b1) {
+        if (rd >= rounds) return;
+        const Z *o = rec + 2 * (int64_t)rd * h;
+        if (has0) {
+            a0 = o[2 * lane];
+            b0 = o[2 * lane + 1];
+        }
+        if (has1) {
+            a1 = o[2 * (lane + 64)];
+            b1 = o[2 * (lane + 64) + 1];
+        }
+    };
+    fetch(0, cs0, e0, cs1, e1);
+    for (int rd = 0; rd < rounds; ++rd) {
+        Z ncs0 = cs0, ne0 = e0, ncs1 = cs1, ne1 = e1;
+        fetch(rd + 1, ncs0, ne0, ncs1, ne1);
+        const int round = rd % (m - 1);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const bool has = u == 0 ? has0 : has1;
+            if (!has) continue;
+            const int k = lane + 64 * u;
+            const Z cs = u == 0 ? cs0 : cs1, e = u == 0 ? e0 : e1;
+            int p, q;
+            rr_pair(m, round, k, p, q);
+            if (q >= n) continue;
+            const Z vp = row[p], vq = row[q];
+            const Z j10b = zscale(e, -cs.y), j11b = zscale(e, cs.x);
+            row[p] = zadd(zscale(vp, cs.x), zmul(vq, j10b));
+            row[q] = zadd(zscale(vp, cs.y), zmul(vq, j11b));
+        }
+        wave_sync();
+        cs0 = ncs0;
+        e0 = ne0;
+        cs1 = ncs1;
+        e1 = ne1;
+    }
+    for (int j = lane; j < n; j += 64) Y[(int64_t)i * n + perm[j]] = row[j];
+}
+
 __global__ void k_identity(Z *V, int n) {
     const int64_t total = (int64_t)n * n;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -593,8 +1067,8 @@ inline int grid_for(int64_t total) {
 }  // namespace
 
 size_t chol_work_elems(int n) {
-    const size_t np = chol_np(n), nt = np / 16;
-    return 2 * np * np + nt * 256 + (np + 1) / 2 + 1;
+    const size_t np = chol_np(n);
+    return 2 * np * np + (np + 1) / 2 + 1;
 }
 
 void chol_qr_factor(const Z *G, int n, double shift, Z *B, Z *work, int *info,
@@ -605,7 +1079,13 @@ void chol_qr_factor(const Z *G, int n, double shift, Z *B, Z *work, int *info,
     check_launch("k_chol_blocked");
 }
 
-size_t jacobi_work_elems(int n) { return (size_t)3 * n * n; }
+size_t jacobi_work_elems(int n) {
+    // The mid-size path's rotation record grows with n up to kJacobiMid;
+    // smaller orders than n use it too (locking shrinks the problem).
+    size_t e = (size_t)3 * n * n;
+    if (n > kJacobiLds) e = std::max(e, jacobi_mid_elems(std::min(n, kJacobiMid)));
+    return e;
+}
 
 void hermitise(Z *G, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_hermitise, dim3(grid_for((int64_t)n * n)), dim3(256),
@@ -724,11 +1204,14 @@ static int jacobi_max_sweeps() {
 }
 
 void jacobi_check_status(int n, int st) {
-    if (n > kJacobiLds) return;   // the sweep path checks as it goes
+    if (n > kJacobiMid) return;   // the sweep path checks as it goes
     if (st == -2) throw Error(5, "jacobi: non-finite matrix");
-    if (st == -1)
+    if (st == -1) {
+        const int cap = n > kJacobiLds ? std::min(jacobi_max_sweeps(), kRotSweeps)
+                                       : jacobi_max_sweeps();
         throw Error(7, "jacobi: the reduced eigenproblem did not converge in " +
-                           std::to_string(jacobi_max_sweeps()) + " sweeps");
+                           std::to_string(cap) + " sweeps");
+    }
 }
 
 void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
@@ -743,6 +1226,27 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
         hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(threads), 0, s, (const Z *)A, n,
                            max_sweeps, w, Y, dstatus);
         check_launch("k_jacobi_small");
+        if (hstatus) {
+            CHASE_HIP(hipMemcpyAsync(hstatus, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+            return;
+        }
+        CHASE_HIP(hipMemcpyAsync(hwork, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+        CHASE_HIP(hipStreamSynchronize(s));
+        int st = 0;
+        std::memcpy(&st, hwork, sizeof(int));
+        jacobi_check_status(n, st);
+        return;
+    }
+    if (n <= kJacobiMid) {
+        // Two launches, the status word read with the caller's results.
+        const int max_sweeps = std::min(jacobi_max_sweeps(), kRotSweeps);
+        int *dstatus = reinterpret_cast<int *>(work);
+        hipLaunchKernelGGL(k_jacobi_mid, dim3(1), dim3(kJacobiMidThreads), 0, s, (const Z *)A,
+                           n, max_sweeps, w, work);
+        check_launch("k_jacobi_mid");
+        hipLaunchKernelGGL(k_jacobi_apply_rot, dim3((n + kRotRowsPerBlock - 1) / kRotRowsPerBlock),
+                           dim3(64 * kRotRowsPerBlock), 0, s, (const Z *)work, n, Y);
+        check_launch("k_jacobi_apply_rot");
         if (hstatus) {
             CHASE_HIP(hipMemcpyAsync(hstatus, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
             return;

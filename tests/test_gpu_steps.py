@@ -196,10 +196,12 @@ def test_rayleigh_ritz_vs_oracle():
     assert np.abs(V.conj().T @ V - np.eye(n)).max() <= 1e-13
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 32, 33, 64, 65, 141])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 32, 33, 64, 65, 100, 130, 139, 140, 141])
 def test_heevj_vs_oracle(n):
-    """Orders up to 64 take the one-launch LDS kernel, larger ones the
-    per-round launches; both against the oracle."""
+    """Orders up to 64 take the one-launch LDS kernel, 65..140 the packed-LDS
+    kernel with recorded rotations (130: an odd number of pairs per round,
+    139: a phantom index), larger ones the per-round launches; all against
+    the oracle."""
     torch_cuda()
     G = synth.random_block(n, n, seed=n)
     G = 0.5 * (G + G.conj().T)
@@ -214,10 +216,10 @@ def test_heevj_vs_oracle(n):
 
 def test_heevj_reports_non_convergence(monkeypatch):
     """A sweep cap below what the matrix needs is reported as an error by
-    both Jacobi paths (the diagnostic override of the cap)."""
+    all three Jacobi paths (the diagnostic override of the cap)."""
     torch_cuda()
     monkeypatch.setenv("CHASE_JACOBI_MAX_SWEEPS", "1")
-    for n in (40, 100):
+    for n in (40, 100, 160):
         G = synth.random_block(n, n, seed=3)
         G = 0.5 * (G + G.conj().T)
         with pytest.raises(chase.ChaseError, match="did not converge in 1 sweeps"):
