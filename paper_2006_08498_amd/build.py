@@ -32,11 +32,11 @@ SOURCES = ["k_filter.hip", "k_filter_wide.hip", "k_filter32.hip", "k_filter_fuse
 SYNTH_SOURCES = ["synth_dev.hip"]
 
 
-# MFMA register form per source: the VGPR form keeps the accumulators of the
-# narrower tiles in place; the widest filter tiles need the AGPR file.
+# MFMA register form per source: the VGPR form keeps the filter tiles'
+# accumulators in place through their k loops.
 VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
-EXTRA = {"k_filter.hip": VGPR_FORM, "k_filter32.hip": VGPR_FORM, "k_blas.hip": VGPR_FORM,
-         "k_dense.hip": VGPR_FORM, "k_filter_fused.hip": VGPR_FORM}
+EXTRA = {"k_filter.hip": VGPR_FORM, "k_filter_wide.hip": VGPR_FORM, "k_filter32.hip": VGPR_FORM,
+         "k_blas.hip": VGPR_FORM, "k_dense.hip": VGPR_FORM, "k_filter_fused.hip": VGPR_FORM}
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -168,6 +168,7 @@ void filter_gemm(const Z *H, int64_t ldh, int64_t N64, const Z *Y, int64_t ldy,
                  double b, double g, Z *part, hipStream_t s,
                  hipEvent_t after_mfma) {
     if (n <= 0 || N64 <= 0) return;
+    check_buffer_strides(ldh, ldy);
     const int N = (int)N64;
     const auto pieces = filter_pieces(N64, n);
     for (size_t i = 0; i < pieces.size(); ++i) {
@@ -205,6 +206,7 @@ void filter_gemm_group(const FilterCall *calls, int count, hipStream_t s) {
     std::vector<std::vector<std::pair<FilterCall, FilterPlan>>> rounds;
     for (int i = 0; i < count; ++i) {
         if (calls[i].n <= 0 || calls[i].N <= 0) continue;
+        check_buffer_strides(calls[i].ldh, calls[i].ldy);
         const auto pieces = filter_pieces(calls[i].N, calls[i].n);
         if (rounds.size() < pieces.size()) rounds.resize(pieces.size());
         for (size_t r = 0; r < pieces.size(); ++r) {

@@ -1,9 +1,7 @@
 // Filter GEMM kernel template, shared by the two translation units that
-// instantiate it (k_filter.hip: tile widths 1-8, built with the VGPR form of
-// MFMA; k_filter_wide.hip: widths 9-10, built with the AGPR form).  The
-// register allocator keeps the accumulators in place only with the right
-// form for each width (otherwise it moves them between register files every
-// k step).
+// instantiate it (k_filter.hip: tile widths 1-8; k_filter_wide.hip: widths
+// 9-10; both built with the VGPR form of MFMA, in which the register
+// allocator keeps every width's accumulators in place through the k loop).
 #pragma once
 
 #include "common.h"
@@ -55,6 +53,21 @@ struct FilterGroupArgs {
     FilterArgs p[kMaxGroup];
 };
 
+// Raw buffer over `bytes` bytes at `base` (loads past them return zero),
+// and one 16-byte load from it at a per-lane and a scalar byte offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int64_t bytes) {
+    const int num = (int)(bytes <= 0 ? 0 : bytes < 0x7fffffff ? bytes : 0x7fffffff);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, num, 0x00020000);
+}
+__device__ __forceinline__ Z buffer_load_z(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return __builtin_bit_cast(Z, v);
+}
+
+// H steps kept in flight by the wide tiles.
+constexpr int kHRing = 4;
+
 // Workgroup `id` of one GEMM's grid: a 64-row block of H times a block of
 // 16*WN columns over one K range.
 template <int WN, int PD, bool FUSED>
@@ -64,7 +77,9 @@ __device__ __forceinline__ void filter_tile(
     double b, double g, int rb_count, int cb_count, int splits, int kchunk,
     Z *__restrict__ part, int id) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // (readfirstlane: the compiler then knows the wave index, and the buffer
+    // bases below, are uniform across the wave)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
 
     const int xcd = id & 7;
@@ -118,27 +133,61 @@ __device__ __forceinline__ void filter_tile(
 
     const int nsteps = (kend - kbeg) >> 2;
     if constexpr (PD == 0) {
-        // Wide tiles (MFMA-bound): the operands of step s + 1 load while
-        // step s computes; at 4*WN MFMAs per step this covers the latency.
+        // Wide tiles (MFMA-bound).  H streams from HBM, Y mostly from L2:
+        // a ring of kHRing steps of H loads is kept in flight (one k step
+        // is 4 WN MFMAs, shorter than HBM latency under load), and Y is
+        // loaded one step ahead into the other of two buffers.  Step t
+        // uses H stage t % kHRing and Y buffer t % 2.  The loads are buffer
+        // loads: a per-lane 32-bit offset plus a scalar offset from a base
+        // that moves once per ring turn, so a step costs no 64-bit address
+        // registers (which the accumulators of the widest tiles need).
+        constexpr int DH = kHRing;
+        static_assert(DH % 2 == 0, "the Y buffer parity follows the H stage");
+        const char *hbase = reinterpret_cast<const char *>(H + row0 + (int64_t)kbeg * ldh);
+        const char *ybase = reinterpret_cast<const char *>(Y + (int64_t)kbeg * ldy);
+        const int hs = (int)(4 * ldh * (int64_t)sizeof(Z));   // bytes per k step
+        const int ys = (int)(4 * ldy * (int64_t)sizeof(Z));
+        const int hvo = (int)((arow - row0 + (int64_t)q * ldh) * sizeof(Z));
+        int yvo[WN];
+#pragma unroll
+        for (int c = 0; c < WN; ++c) yvo[c] = (int)(((int64_t)q * ldy + ycol[c]) * sizeof(Z));
+        Z hr[DH];
+        Z yb[2][WN];
+        // Each buffer covers only the steps left from its base: loads of
+        // steps past the end return zeros (hardware range check), so the
+        // loop needs no guards (a guarded load makes the compiler wait for
+        // every load in flight) and the extra steps add nothing.
+        auto h_rsrc = [&](int st) {
+            return buffer_rsrc(hbase + (int64_t)st * hs, (int64_t)(nsteps - st) * hs);
+        };
+        auto y_rsrc = [&](int st) {
+            return buffer_rsrc(ybase + (int64_t)st * ys, (int64_t)(nsteps - st) * ys);
+        };
+        __amdgpu_buffer_rsrc_t rh = h_rsrc(0), ry = y_rsrc(0);
+#define CHASE_LOADH(stage, rel) hr[stage] = buffer_load_z(rh, hvo, (rel) * hs);
+#define CHASE_LOADY(buf, rel)                                                 \
+    {                                                                         \
+        _Pragma("unroll") for (int c = 0; c < WN; ++c)                        \
+            yb[buf][c] = buffer_load_z(ry, yvo[c], (rel) * ys);               \
+    }
         if (nsteps > 0) {
-            Z h = *hp;
-            Z y[WN];
 #pragma unroll
-            for (int c = 0; c < WN; ++c) y[c] = yp[ycol[c]];
-            for (int st = 0; st + 1 < nsteps; ++st) {
-                const Z *hn_p = hp + (int64_t)(st + 1) * hstep;
-                const Z *yn_p = yp + (int64_t)(st + 1) * ystep;
-                Z hn = *hn_p;
-                Z yn[WN];
-#pragma unroll
-                for (int c = 0; c < WN; ++c) yn[c] = yn_p[ycol[c]];
-                CHASE_KSTEP(h, y);
-                h = hn;
-#pragma unroll
-                for (int c = 0; c < WN; ++c) y[c] = yn[c];
-            }
-            CHASE_KSTEP(h, y);
+            for (int j = 0; j < DH; ++j) CHASE_LOADH(j, j);
+            CHASE_LOADY(0, 0);
         }
+        for (int s0 = 0; s0 < nsteps; s0 += DH) {
+            // rh and ry are based at step s0.
+#pragma unroll
+            for (int j = 0; j < DH; ++j) {
+                CHASE_LOADY((j + 1) & 1, j + 1);
+                CHASE_KSTEP(hr[j], yb[j & 1]);
+                CHASE_LOADH(j, j + DH);
+            }
+            rh = h_rsrc(s0 + DH);
+            ry = y_rsrc(s0 + DH);
+        }
+#undef CHASE_LOADH
+#undef CHASE_LOADY
     } else {
         // Narrow tiles: a register ring of R = PD + 1 k steps, step t in
         // stage t % R.  Before the MFMAs of step t the operands of step
@@ -252,6 +301,14 @@ constexpr int prefetch_depth(int wn) {
     return wn == 1 ? 8 : wn == 2 ? 6 : wn == 3 ? 4 : wn == 4 ? 2 : 0;
 }
 
+
+// The wide tiles address H and Y with 32-bit buffer offsets of up to
+// 2 kHRing k steps (4 columns of H, 4 rows of Y each).
+inline void check_buffer_strides(int64_t ldh, int64_t ldy) {
+    const int64_t lim = ((int64_t)1 << 31) / (2 * kHRing * 4 * (int64_t)sizeof(Z));
+    if (ldh >= lim || ldy >= lim)
+        throw Error(1, "filter: leading dimension too large for 32-bit buffer offsets");
+}
 
 inline int filter_blocks(const FilterPlan &p) {
     return (p.rb + 7) / 8 * 8 * p.cb * p.splits;

@@ -1,5 +1,6 @@
 // Filter GEMM instantiations for the widest tiles (9 and 10 16-column
-// blocks per wave), built with the AGPR form of MFMA (see k_filter_kern.h).
+// blocks per wave), built like the others with the VGPR form of MFMA (see
+// k_filter_kern.h).
 #include "k_filter_kern.h"
 
 namespace chase {
