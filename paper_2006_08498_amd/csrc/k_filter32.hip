@@ -19,6 +19,25 @@ __device__ __forceinline__ v4f mfma32(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// H steps in flight and Y buffers of the wide FP32 tiles (measured on
+// MI355X at N = 24000 against 8 and 2: 16 and 4 are 2-4% faster at widths
+// 5-9; the old full-operand ring of 4-6 steps was 8-32% slower).
+constexpr int h_ring32(int wn) { return wn >= 5 ? 16 : 0; }
+constexpr int y_bufs32(int wn) { return wn >= 5 ? 4 : 0; }
+constexpr int kHRing32Max = 16;
+
+// Raw buffer over `bytes` bytes at `base` (loads past them return zero),
+// and one 8-byte load from it at a per-lane and a scalar byte offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc32(const void *base, int64_t bytes) {
+    const int num = (int)(bytes <= 0 ? 0 : bytes < 0x7fffffff ? bytes : 0x7fffffff);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, num, 0x00020000);
+}
+__device__ __forceinline__ C buffer_load_c(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __builtin_bit_cast(C, v);
+}
+
 template <int WN, int PD, bool FUSED>
 __global__ __launch_bounds__(256) void k_filter32(
     const C *__restrict__ H, int64_t ldh, int N, const C *__restrict__ Y,
@@ -26,7 +45,7 @@ __global__ __launch_bounds__(256) void k_filter32(
     float b, float g, int rb_count, int cb_count, int splits, int kchunk,
     C *__restrict__ part) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform buffer bases
     const int r = lane & 15, q = lane >> 4;
     const int id = blockIdx.x;
     const int xcd = id & 7;
@@ -69,7 +88,62 @@ __global__ __launch_bounds__(256) void k_filter32(
             ci[c] = mfma32((hv).y, (yv)[c].x, ci[c]);                         \
     }
     const int nsteps = (kend - kbeg) >> 2;
-    {
+    if constexpr (WN >= 5) {
+        // Wide tiles: a ring of DH steps of H loads in flight and Y loaded
+        // YB - 1 steps ahead into YB buffers (step t uses H stage t % DH and
+        // Y buffer t % YB), through raw buffer loads whose base moves once
+        // per ring turn and covers only the steps left, so loads past the
+        // end return zero and the loop needs no guards (the FP64 kernel's
+        // scheme, with twice the steps in flight: an FP32 MFMA takes half as
+        // long).
+        constexpr int DH = h_ring32(WN), YB = y_bufs32(WN);
+        static_assert(DH % YB == 0, "the Y buffer follows the H stage");
+        const char *hbase = reinterpret_cast<const char *>(H + row0 + (int64_t)kbeg * ldh);
+        const char *ybase = reinterpret_cast<const char *>(Y + (int64_t)kbeg * ldy);
+        const int hs = (int)(4 * ldh * (int64_t)sizeof(C));
+        const int ys = (int)(4 * ldy * (int64_t)sizeof(C));
+        const int hvo = (int)((arow - row0 + (int64_t)q * ldh) * sizeof(C));
+        int yvo[WN];
+#pragma unroll
+        for (int c = 0; c < WN; ++c) yvo[c] = (int)(((int64_t)q * ldy + ycol[c]) * sizeof(C));
+        C hr[DH];
+        C yb[YB][WN];
+        auto h_rsrc = [&](int st) {
+            return buffer_rsrc32(hbase + (int64_t)st * hs, (int64_t)(nsteps - st) * hs);
+        };
+        auto y_rsrc = [&](int st) {
+            return buffer_rsrc32(ybase + (int64_t)st * ys, (int64_t)(nsteps - st) * ys);
+        };
+        __amdgpu_buffer_rsrc_t rh = h_rsrc(0), ry = y_rsrc(0);
+#define CHASE_LOADH32(stage, rel) hr[stage] = buffer_load_c(rh, hvo, (rel) * hs);
+#define CHASE_LOADY32(buf, rel)                                               \
+    {                                                                         \
+        _Pragma("unroll") for (int c = 0; c < WN; ++c)                        \
+            yb[buf][c] = buffer_load_c(ry, yvo[c], (rel) * ys);               \
+    }
+        if (nsteps > 0) {
+#pragma unroll
+            for (int j = 0; j < DH; ++j) CHASE_LOADH32(j, j);
+#pragma unroll
+            for (int j = 0; j < YB - 1; ++j) CHASE_LOADY32(j, j);
+        }
+        for (int s0 = 0; s0 < nsteps; s0 += DH) {
+            // rh and ry are based at step s0.
+#pragma unroll
+            for (int j = 0; j < DH; ++j) {
+                CHASE_LOADY32((j + YB - 1) % YB, j + YB - 1);
+                // (the loads stay ahead of the step's MFMAs: left alone the
+                // scheduler sinks them next to their use)
+                __builtin_amdgcn_sched_barrier(0);
+                CHASE_KSTEP32(hr[j], yb[j % YB]);
+                CHASE_LOADH32(j, j + DH);
+            }
+            rh = h_rsrc(s0 + DH);
+            ry = y_rsrc(s0 + DH);
+        }
+#undef CHASE_LOADH32
+#undef CHASE_LOADY32
+    } else {
         // Register ring of R = PD + 1 k steps (step t in stage t % R); the
         // operands of step t + PD load before the MFMAs of step t.
         constexpr int R = PD + 1;
@@ -298,6 +372,12 @@ void filter32_gemm(const C *H, int64_t ldh, int64_t N64, const C *Y, int64_t ldy
                    const C *X, int64_t ldx, C *W, int64_t ldw, int n, float a,
                    float b, float g, C *part, hipStream_t s, hipEvent_t after_mfma) {
     if (n <= 0 || N64 <= 0) return;
+    {
+        // 32-bit buffer offsets of up to 2 h_ring32 k steps (wide tiles)
+        const int64_t lim = ((int64_t)1 << 31) / (2 * kHRing32Max * 4 * (int64_t)sizeof(C));
+        if (ldh >= lim || ldy >= lim)
+            throw Error(1, "filter: leading dimension too large for 32-bit buffer offsets");
+    }
     const int N = (int)N64;
     const auto pieces = filter32_pieces(N64, n);
     for (size_t i = 0; i < pieces.size(); ++i) {
