@@ -65,10 +65,14 @@ __device__ __forceinline__ Z buffer_load_z(__amdgpu_buffer_rsrc_t r, int voff, i
     return __builtin_bit_cast(Z, v);
 }
 
-// H steps kept in flight by the wide tiles (measured on MI355X at
-// N = 24000: 8 against 4 is 1.8% faster at 9 tiles; 6 is best at 5-8).
-constexpr int h_ring(int wn) { return wn >= 9 ? 8 : 6; }
-constexpr int kHRingMax = 8;
+// Ring of each tile width: H steps in flight (the kernels' PD) and Y
+// buffers.  Measured on MI355X at N = 24000: 8 H steps against 4 are 1.8%
+// faster at 9 tiles, 6 are best at 5-8; the narrow tiles carry Y as far
+// ahead as H (2-5% faster at widths 1-4 than the full-operand rings of 9,
+// 7, 5 and 3 steps with 64-bit addresses they replaced).
+constexpr int h_ring(int wn) { return wn >= 9 ? 8 : wn >= 4 ? 6 : wn == 3 ? 8 : wn == 2 ? 12 : 16; }
+constexpr int y_bufs(int wn) { return wn >= 5 ? 2 : h_ring(wn); }
+constexpr int kHRingMax = 16;
 
 // Workgroup `id` of one GEMM's grid: a 64-row block of H times a block of
 // 16*WN columns over one K range.
@@ -134,17 +138,21 @@ __device__ __forceinline__ void filter_tile(
     }
 
     const int nsteps = (kend - kbeg) >> 2;
-    if constexpr (PD == 0) {
-        // Wide tiles (MFMA-bound).  H streams from HBM, Y mostly from L2:
-        // a ring of h_ring(WN) steps of H loads is kept in flight (one k step
-        // is 4 WN MFMAs, shorter than HBM latency under load), and Y is
-        // loaded one step ahead into the other of two buffers.  Step t
-        // uses H stage t % h_ring(WN) and Y buffer t % 2.  The loads are buffer
+    {
+        // A ring of PD steps of H loads in flight and Y loaded YB - 1 steps
+        // ahead into YB buffers (step t uses H stage t % PD and Y buffer
+        // t % YB).  H streams from HBM; Y comes mostly from L2, so the wide
+        // (MFMA-bound) tiles load it one step ahead, and the narrow ones,
+        // whose k steps are short, as far ahead as H.  The loads are buffer
         // loads: a per-lane 32-bit offset plus a scalar offset from a base
         // that moves once per ring turn, so a step costs no 64-bit address
-        // registers (which the accumulators of the widest tiles need).
-        constexpr int DH = h_ring(WN);
-        static_assert(DH % 2 == 0, "the Y buffer parity follows the H stage");
+        // registers (which the accumulators of the widest tiles need), and
+        // each buffer covers only the steps left, so loads past the end
+        // return zeros (hardware range check) and the loop needs no guards
+        // (a guarded load makes the compiler wait for every load in flight;
+        // the extra steps add nothing).
+        constexpr int DH = PD, YB = y_bufs(WN);
+        static_assert(DH % YB == 0, "the Y buffer follows the H stage");
         const char *hbase = reinterpret_cast<const char *>(H + row0 + (int64_t)kbeg * ldh);
         const char *ybase = reinterpret_cast<const char *>(Y + (int64_t)kbeg * ldy);
         const int hs = (int)(4 * ldh * (int64_t)sizeof(Z));   // bytes per k step
@@ -154,11 +162,7 @@ __device__ __forceinline__ void filter_tile(
 #pragma unroll
         for (int c = 0; c < WN; ++c) yvo[c] = (int)(((int64_t)q * ldy + ycol[c]) * sizeof(Z));
         Z hr[DH];
-        Z yb[2][WN];
-        // Each buffer covers only the steps left from its base: loads of
-        // steps past the end return zeros (hardware range check), so the
-        // loop needs no guards (a guarded load makes the compiler wait for
-        // every load in flight) and the extra steps add nothing.
+        Z yb[YB][WN];
         auto h_rsrc = [&](int st) {
             return buffer_rsrc(hbase + (int64_t)st * hs, (int64_t)(nsteps - st) * hs);
         };
@@ -175,14 +179,18 @@ __device__ __forceinline__ void filter_tile(
         if (nsteps > 0) {
 #pragma unroll
             for (int j = 0; j < DH; ++j) CHASE_LOADH(j, j);
-            CHASE_LOADY(0, 0);
+#pragma unroll
+            for (int j = 0; j < YB - 1; ++j) CHASE_LOADY(j, j);
         }
         for (int s0 = 0; s0 < nsteps; s0 += DH) {
             // rh and ry are based at step s0.
 #pragma unroll
             for (int j = 0; j < DH; ++j) {
-                CHASE_LOADY((j + 1) & 1, j + 1);
-                CHASE_KSTEP(hr[j], yb[j & 1]);
+                CHASE_LOADY((j + YB - 1) % YB, j + YB - 1);
+                // (the loads stay ahead of the step's MFMAs: left alone the
+                // scheduler sinks them next to their use)
+                __builtin_amdgcn_sched_barrier(0);
+                CHASE_KSTEP(hr[j], yb[j % YB]);
                 CHASE_LOADH(j, j + DH);
             }
             rh = h_rsrc(s0 + DH);
@@ -190,43 +198,6 @@ __device__ __forceinline__ void filter_tile(
         }
 #undef CHASE_LOADH
 #undef CHASE_LOADY
-    } else {
-        // Narrow tiles: a register ring of R = PD + 1 k steps, step t in
-        // stage t % R.  Before the MFMAs of step t the operands of step
-        // t + PD are loaded into the stage step t - 1 just freed, so each
-        // wave keeps PD steps of loads in flight (short steps need many).
-        // The steady-state loop has no bounds checks; the remainder does.
-        constexpr int R = PD + 1;
-        Z hr[R];
-        Z yr[R][WN];
-#define CHASE_LOAD(stage, step)                                               \
-    {                                                                         \
-        hr[stage] = hp[(int64_t)(step) * hstep];                              \
-        _Pragma("unroll") for (int c = 0; c < WN; ++c)                        \
-            yr[stage][c] = yp[(int64_t)(step) * ystep + ycol[c]];             \
-    }
-#pragma unroll
-        for (int j = 0; j < PD; ++j)
-            if (j < nsteps) CHASE_LOAD(j, j);
-        int s0 = 0;
-        for (; s0 + R + PD <= nsteps; s0 += R) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                CHASE_LOAD((j + PD) % R, s0 + j + PD);
-                CHASE_KSTEP(hr[j], yr[j]);
-            }
-        }
-        for (; s0 < nsteps; s0 += R) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int st = s0 + j;
-                if (st < nsteps) {
-                    if (st + PD < nsteps) CHASE_LOAD((j + PD) % R, st + PD);
-                    CHASE_KSTEP(hr[j], yr[j]);
-                }
-            }
-        }
-#undef CHASE_LOAD
     }
     const int k = kbeg + 4 * nsteps;
     if (k < kend) {
@@ -295,16 +266,10 @@ __global__ __launch_bounds__(256) void k_filter_group(const FilterGroupArgs G) {
                                    A.kchunk, A.part, lid);
 }
 
-// Prefetch depth per tile width (0 = one step ahead, no ring): narrow
-// tiles have short k steps and need more loads in flight to cover HBM
-// latency; measured on MI355X at N = 24000 the ring helps up to WN = 4 and
-// costs registers (and speed) beyond.
-constexpr int prefetch_depth(int wn) {
-    return wn == 1 ? 8 : wn == 2 ? 6 : wn == 3 ? 4 : wn == 4 ? 2 : 0;
-}
+// The kernels' PD: the H ring of the width.
+constexpr int prefetch_depth(int wn) { return h_ring(wn); }
 
-
-// The wide tiles address H and Y with 32-bit buffer offsets of up to
+// The kernels address H and Y with 32-bit buffer offsets of up to
 // 2 h_ring(WN) k steps (4 columns of H, 4 rows of Y each).
 inline void check_buffer_strides(int64_t ldh, int64_t ldy) {
     const int64_t lim = ((int64_t)1 << 31) / (2 * kHRingMax * 4 * (int64_t)sizeof(Z));
