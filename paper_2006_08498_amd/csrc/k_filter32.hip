@@ -19,11 +19,12 @@ __device__ __forceinline__ v4f mfma32(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// H steps in flight and Y buffers of the wide FP32 tiles (measured on
-// MI355X at N = 24000 against 8 and 2: 16 and 4 are 2-4% faster at widths
-// 5-9; the old full-operand ring of 4-6 steps was 8-32% slower).
-constexpr int h_ring32(int wn) { return wn >= 5 ? 16 : 0; }
-constexpr int y_bufs32(int wn) { return wn >= 5 ? 4 : 0; }
+// H steps in flight and Y buffers per FP32 tile width (measured on MI355X
+// at N = 24000 against 8 and 2: 16 and 4 are 2-4% faster at widths 5-9;
+// the full-operand ring of 4-6 steps they replaced was 8-32% slower).  The
+// narrow tiles carry Y as far ahead as H.
+constexpr int h_ring32(int wn) { return wn >= 5 ? 16 : wn >= 3 ? 12 : 16; }
+constexpr int y_bufs32(int wn) { return wn >= 5 ? 4 : h_ring32(wn); }
 constexpr int kHRing32Max = 16;
 
 // Raw buffer over `bytes` bytes at `base` (loads past them return zero),
@@ -88,14 +89,13 @@ __global__ __launch_bounds__(256) void k_filter32(
             ci[c] = mfma32((hv).y, (yv)[c].x, ci[c]);                         \
     }
     const int nsteps = (kend - kbeg) >> 2;
-    if constexpr (WN >= 5) {
-        // Wide tiles: a ring of DH steps of H loads in flight and Y loaded
-        // YB - 1 steps ahead into YB buffers (step t uses H stage t % DH and
-        // Y buffer t % YB), through raw buffer loads whose base moves once
-        // per ring turn and covers only the steps left, so loads past the
-        // end return zero and the loop needs no guards (the FP64 kernel's
-        // scheme, with twice the steps in flight: an FP32 MFMA takes half as
-        // long).
+    {
+        // A ring of DH steps of H loads in flight and Y loaded YB - 1 steps
+        // ahead into YB buffers (step t uses H stage t % DH and Y buffer
+        // t % YB), through raw buffer loads whose base moves once per ring
+        // turn and covers only the steps left, so loads past the end return
+        // zero and the loop needs no guards (the FP64 kernel's scheme, with
+        // more steps in flight: an FP32 MFMA takes half as long).
         constexpr int DH = h_ring32(WN), YB = y_bufs32(WN);
         static_assert(DH % YB == 0, "the Y buffer follows the H stage");
         const char *hbase = reinterpret_cast<const char *>(H + row0 + (int64_t)kbeg * ldh);
@@ -143,40 +143,6 @@ __global__ __launch_bounds__(256) void k_filter32(
         }
 #undef CHASE_LOADH32
 #undef CHASE_LOADY32
-    } else {
-        // Register ring of R = PD + 1 k steps (step t in stage t % R); the
-        // operands of step t + PD load before the MFMAs of step t.
-        constexpr int R = PD + 1;
-        C hr[R];
-        C yr[R][WN];
-#define CHASE_LOAD32(stage, step)                                             \
-    {                                                                         \
-        hr[stage] = hp[(int64_t)(step) * hstep];                              \
-        _Pragma("unroll") for (int c = 0; c < WN; ++c)                        \
-            yr[stage][c] = yp[(int64_t)(step) * ystep + ycol[c]];             \
-    }
-#pragma unroll
-        for (int j = 0; j < PD; ++j)
-            if (j < nsteps) CHASE_LOAD32(j, j);
-        int s0 = 0;
-        for (; s0 + R + PD <= nsteps; s0 += R) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                CHASE_LOAD32((j + PD) % R, s0 + j + PD);
-                CHASE_KSTEP32(hr[j], yr[j]);
-            }
-        }
-        for (; s0 < nsteps; s0 += R) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int st = s0 + j;
-                if (st < nsteps) {
-                    if (st + PD < nsteps) CHASE_LOAD32((j + PD) % R, st + PD);
-                    CHASE_KSTEP32(hr[j], yr[j]);
-                }
-            }
-        }
-#undef CHASE_LOAD32
     }
     const int k = kbeg + 4 * nsteps;
     if (k < kend) {
@@ -247,12 +213,8 @@ __global__ __launch_bounds__(256) void k_filter32_reduce(
     }
 }
 
-// Prefetch depth per tile width, measured on MI355X at N = 24000 and 60000:
-// width 7 needs the 6-deep ring (89-95 -> 114-124 TFLOP/s); widths 8-10 run
-// best at 4.
-constexpr int prefetch_depth32(int wn) {
-    return wn <= 4 ? 8 : wn <= 7 ? 6 : 4;
-}
+// The kernels' PD template argument: the H ring of the width.
+constexpr int prefetch_depth32(int wn) { return h_ring32(wn); }
 
 template <int WN>
 void launch32(const FilterPlan &p, const C *H, int64_t ldh, int N, const C *Y,
