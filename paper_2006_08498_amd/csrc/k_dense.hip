@@ -177,8 +177,36 @@ __device__ __forceinline__ int diag_factor(Z (*Ls)[17], Z (*linv)[17]) {
     return 0;
 }
 
+// W = D G D + shift I (D = diag(G)^(-1/2)) in its lower triangle, padded
+// with the identity to 16 nt, and B's blocks below the diagonal blocks set
+// to zero: one 16 x 16 tile per workgroup over the lower tiles (tile b =
+// (I, J), row-major over J <= I), so this O(n^2) pass is spread over the
+// chip rather than left to the factor's single workgroup.
+__global__ __launch_bounds__(256) void k_chol_prep(const Z *__restrict__ G, int n, double shift,
+                                                   Z *__restrict__ B, Z *__restrict__ W) {
+    const int np = 16 * ((n + 15) / 16);
+    const int b = blockIdx.x;
+    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while (I > 0 && I * (I + 1) / 2 > b) --I;
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    const int J = b - I * (I + 1) / 2;
+    const int i = 16 * I + (int)(threadIdx.x >> 4), j = 16 * J + (int)(threadIdx.x & 15);
+    if (j <= i) {
+        Z v{i == j ? 1.0 : 0.0, 0.0};
+        if (i < n) {
+            const double gi = G[(int64_t)i * n + i].x, gj = G[(int64_t)j * n + j].x;
+            const double di = gi > 0.0 ? 1.0 / sqrt(gi) : 0.0;
+            const double dj = gj > 0.0 ? 1.0 / sqrt(gj) : 0.0;
+            v = zscale(G[(int64_t)i * n + j], di * dj);
+            if (i == j) v = Z{v.x + shift, 0.0};
+        }
+        W[(int64_t)i * np + j] = v;
+    }
+    if (I > J && i < n && j < n) B[(int64_t)i * n + j] = Z{0.0, 0.0};
+}
+
 __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restrict__ G, int n,
-                                                               double shift, Z *__restrict__ B,
+                                                               Z *__restrict__ B,
                                                                Z *__restrict__ work,
                                                                int *info) {
     __shared__ Z linv[2][16][17];          // L_kk^{-1}, by step parity
@@ -205,36 +233,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
         if (t == 0) *info = bad;
         return;
     }
-    // W = D G D + shift I, padded with the identity (the lower triangle is
-    // all that is read); B below its diagonal blocks is zero.
-    // (Eight entries per thread in flight: the loads are issued together.)
-    for (int64_t e0 = t; e0 < (int64_t)np * np; e0 += 8 * kCholThreads) {
-        Z g[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t e = e0 + (int64_t)u * kCholThreads;
-            const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
-            g[u] = (e < (int64_t)np * np && j <= i && i < n) ? G[(int64_t)i * n + j]
-                                                              : Z{0.0, 0.0};
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t e = e0 + (int64_t)u * kCholThreads;
-            const int i = (int)(e / np), j = (int)(e - (int64_t)i * np);
-            if (e >= (int64_t)np * np || j > i) continue;
-            Z v{i == j ? 1.0 : 0.0, 0.0};
-            if (i < n) {
-                v = zscale(g[u], dsc[i] * dsc[j]);
-                if (i == j) v = Z{v.x + shift, 0.0};
-            }
-            W[e] = v;
-        }
-    }
-    for (int64_t e = t; e < (int64_t)n * n; e += kCholThreads) {
-        const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
-        if (i / 16 < j / 16) B[e] = Z{0.0, 0.0};
-    }
-    __syncthreads();
+    // W (the scaled, shifted, padded lower triangle) and the zero blocks of
+    // B were written by k_chol_prep.
 
     // Block (i, k) of X, in accumulator layout, to X and to B = D X^H.
     auto put_x = [&](int i, int k, const v4d &xr, const v4d &xi) {
@@ -337,8 +337,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
             const int m = nt - k - 1;
             const int tiles = m * (m + 1) / 2;
             const int jobs = k + tiles;
-            for (int u = wave - 1; u < jobs; u += kCholWaves - 1) {
-                if (u < k) {
+            int u = wave - 1;
+            for (; u < k; u += kCholWaves - 1) {
+                {
                     const int j = u;
                     v4d cr{0, 0, 0, 0}, ci{0, 0, 0, 0};
                     const Z *Lk = W + kk0 * np;
@@ -372,22 +373,40 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
                     put_x(k, j, xr, xi);
                     continue;
                 }
-                // Trailing tile number tt (row-major over k < j <= i),
-                // skipping (k+1, k+1), which is tile 0.
-                const int tt = u - k + 1;
-                if (tt >= tiles) continue;
+            }
+            // Trailing tile number tt = u - k + 1 (row-major over k < j <= i),
+            // skipping (k+1, k+1), which is tile 0.  The next tile's W is
+            // loaded before the current tile's products, so its L2 latency
+            // overlaps them.
+            auto tile_at = [&](int uu, int &i, int &j) {
+                const int tt = uu - k + 1;
+                if (uu >= jobs || tt >= tiles) return false;
                 int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
                 while (ii * (ii + 1) / 2 > tt) --ii;
                 while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
-                const int i = k + 1 + ii, j = k + 1 + tt - ii * (ii + 1) / 2;
-                Z *Wij = W + (int64_t)16 * i * np + 16 * j;
-                v4d cr, ci;
+                i = k + 1 + ii;
+                j = k + 1 + tt - ii * (ii + 1) / 2;
+                return true;
+            };
+            auto load_w = [&](int i, int j, v4d &cr, v4d &ci) {
+                const Z *Wij = W + (int64_t)16 * i * np + 16 * j;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const Z w = Wij[(int64_t)(q + 4 * v) * np + r];
                     cr[v] = w.x;
                     ci[v] = w.y;
                 }
+            };
+            int ni = 0, nj = 0;
+            v4d nr{0, 0, 0, 0}, nim{0, 0, 0, 0};
+            bool have = tile_at(u, ni, nj);
+            if (have) load_w(ni, nj, nr, nim);
+            while (have) {
+                const int i = ni, j = nj;
+                v4d cr = nr, ci = nim;
+                u += kCholWaves - 1;
+                have = tile_at(u, ni, nj);
+                if (have) load_w(ni, nj, nr, nim);
                 if (lds_panel) {
                     zblock_mac(cr, ci,
                                [&](int s) {
@@ -405,6 +424,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_blocked(const Z *__restri
                                },
                                [&](int s) { return zconj(Ljk[(int64_t)r * np + 4 * s + q]); });
                 }
+                Z *Wij = W + (int64_t)16 * i * np + 16 * j;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) Wij[(int64_t)(q + 4 * v) * np + r] = Z{cr[v], ci[v]};
             }
@@ -1074,8 +1094,11 @@ size_t chol_work_elems(int n) {
 void chol_qr_factor(const Z *G, int n, double shift, Z *B, Z *work, int *info,
                     hipStream_t s) {
     if (n < 1 || n > 1024) throw Error(7, "chol_qr_factor: order out of range");
-    hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(kCholThreads), 0, s, G, n, shift, B, work,
-                       info);
+    const int nt = (n + 15) / 16;
+    hipLaunchKernelGGL(k_chol_prep, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, G, n,
+                       shift, B, work);
+    check_launch("k_chol_prep");
+    hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(kCholThreads), 0, s, G, n, B, work, info);
     check_launch("k_chol_blocked");
 }
 
