@@ -205,6 +205,16 @@ GramPlan gram_plan(int64_t N, int p, int q, bool herm) {
     ch = (ch + 15) & ~int64_t(15);
     g.chunk = (int)ch;
     g.chunks = (int)((N + ch - 1) / ch);
+    // Chunk s runs on XCD s mod 8: a count that is not a multiple of 8
+    // leaves some XCDs a chunk more than the rest (10 chunks at n = 400 gave
+    // two XCDs twice the work of the other six), so round it up.
+    if (g.chunks > 8 && g.chunks % 8) {
+        const int64_t c8 = (g.chunks + 7) / 8 * 8;
+        ch = (N + c8 - 1) / c8;
+        ch = (ch + 15) & ~int64_t(15);
+        g.chunk = (int)ch;
+        g.chunks = (int)((N + ch - 1) / ch);
+    }
     return g;
 }
 
@@ -644,7 +654,11 @@ void tsmm(const Z *A, int64_t lda, const Z *B, int64_t ldb, int64_t N64, int p,
     if (N64 <= 0 || q <= 0) return;
     const int N = (int)N64;
     const int nb = (q + 15) / 16;
-    const int cb = (nb + 7) / 8;
+    // Upper triangular B: narrow column blocks keep each block's K close to
+    // its own columns (16-column blocks do the triangle's work plus the
+    // diagonal blocks; 80-column blocks did 1.8 times that at q = 140);
+    // 32-column blocks beyond 256 columns keep A's re-reads down.
+    const int cb = upper ? (nb <= 16 ? nb : (nb + 1) / 2) : (nb + 7) / 8;
     const int wn = (nb + cb - 1) / cb;
     const int rb = (N + 63) / 64;
     const dim3 grid((rb + 7) / 8 * 8 * cb);   // row blocks past N return at once

@@ -464,7 +464,6 @@ struct Rot {
     Z e;
     double dp, dq;   // resulting diagonal
     bool active;
-    int p, q;        // the pair (mid-size kernel)
 };
 
 __device__ Rot make_rot(const Z *A, int n, int p, int q) {
@@ -738,7 +737,12 @@ __global__ __launch_bounds__(1024) void k_offnorm(const Z *__restrict__ A,
 // (c, s, e) are recorded, and a second kernel applies them, in order, to
 // the rows of the identity (each row of V is independent: one wave per row,
 // the row in LDS), then writes Y in ascending eigenvalue order.  The
-// rotations and the update formulas are those of k_jacobi_round.
+// rotations and the update formulas are those of k_jacobi_round.  A round's
+// rotations sit in LDS as 32-byte (c, s, e) records; an update takes its
+// pair indices from the round-robin formula and the packed row offsets by
+// arithmetic, so its LDS reads are two records and four matrix entries
+// (pair indices and offset tables read from LDS made every round 30%
+// slower).
 constexpr int kJacobiMid = 140;
 constexpr int kJacobiMidThreads = 1024;
 constexpr int kRotSweeps = 30;   // capacity of the rotation record, in sweeps
@@ -812,7 +816,12 @@ __global__ __launch_bounds__(kJacobiMidThreads) void k_jacobi_mid(const Z *__res
                                                                   double *__restrict__ w,
                                                                   Z *__restrict__ work) {
     __shared__ Z P[kJacobiMid * (kJacobiMid + 1) / 2];
-    __shared__ Rot rot[kJacobiMid / 2];
+    struct RotCS {
+        double c, s, ex, ey;
+    };
+    __shared__ RotCS rcs[kJacobiMid / 2];      // the round's rotations
+    __shared__ double2 rdg[kJacobiMid / 2];    // their resulting diagonal pairs
+    __shared__ int ract[kJacobiMid / 2];
     __shared__ int rb[kJacobiMid];
     __shared__ double red[2][kJacobiMidThreads / 64];
     __shared__ int decide;
@@ -866,10 +875,10 @@ __global__ __launch_bounds__(kJacobiMidThreads) void k_jacobi_mid(const Z *__res
             for (int k = t; k < h; k += kJacobiMidThreads) {
                 int p, q;
                 rr_pair(m, round, k, p, q);
-                Rot R = make_rot_packed(P, n, p, q);
-                R.p = p;
-                R.q = q;
-                rot[k] = R;
+                const Rot R = make_rot_packed(P, n, p, q);
+                rcs[k] = RotCS{R.c, R.s, R.e.x, R.e.y};
+                rdg[k] = double2{R.dp, R.dq};
+                ract[k] = R.active ? 1 : 0;
                 Z *o = rec + 2 * ((int64_t)rounds * h + k);
                 o[0] = Z{R.c, R.s};
                 o[1] = R.e;
@@ -879,33 +888,49 @@ __global__ __launch_bounds__(kJacobiMidThreads) void k_jacobi_mid(const Z *__res
             for (int u = 0; u < kMidBlk; ++u) {
                 const int ka = bka[u], kb = bkb[u];
                 if (ka < 0) continue;
-                const Rot Ra = rot[ka], Rb = rot[kb];
-                const int pa = Ra.p, qa = Ra.q, pb = Rb.p, qb = Rb.q;
+                // Pair indices from the round-robin formula and row offsets
+                // by arithmetic (no LDS reads for either).
+                int pa, qa, pb, qb;
+                rr_pair(m, round, ka, pa, qa);
+                rr_pair(m, round, kb, pb, qb);
                 const bool qa_ok = qa < n, qb_ok = qb < n;
+                auto rbx = [&](int x) { return (x * (2 * n - x - 1)) >> 1; };
                 if (ka == kb) {
-                    P[rb[pa] + pa] = Z{Ra.dp, 0.0};
+                    const double2 d = rdg[ka];
+                    P[rbx(pa) + pa] = Z{d.x, 0.0};
                     if (qa_ok) {
-                        P[rb[qa] + qa] = Z{Ra.dq, 0.0};
-                        if (Ra.active) P[rb[pa] + qa] = Z{0.0, 0.0};
+                        P[rbx(qa) + qa] = Z{d.y, 0.0};
+                        if (ract[ka]) P[rbx(pa) + qa] = Z{0.0, 0.0};
                     }
                     continue;
                 }
+                const RotCS ra = rcs[ka], rbr = rcs[kb];
+                const Z ea{ra.ex, ra.ey}, eb{rbr.ex, rbr.ey};
+                auto get = [&](int x, int y) {
+                    Z v = P[rbx(min(x, y)) + max(x, y)];
+                    if (x > y) v.y = -v.y;
+                    return v;
+                };
+                auto put = [&](int x, int y, Z v) {
+                    if (x > y) v.y = -v.y;
+                    P[rbx(min(x, y)) + max(x, y)] = v;
+                };
                 // The update of k_jacobi_round, A' = J_a^H M J_b, written with
                 // J = [[c, s], [-s e, c e]] so that each 2 x 2 factor costs two
                 // complex products and four real-scaled sums.
                 const Z zero{0.0, 0.0};
-                const Z m00 = pk_get(P, rb, pa, pb);
-                const Z m01 = qb_ok ? pk_get(P, rb, pa, qb) : zero;
-                const Z m10 = qa_ok ? pk_get(P, rb, qa, pb) : zero;
-                const Z m11 = (qa_ok && qb_ok) ? pk_get(P, rb, qa, qb) : zero;
-                const Z u0 = zmul_f(Rb.e, m01), u1 = zmul_f(Rb.e, m11);
-                const Z t00 = zaxpby(Rb.c, m00, -Rb.s, u0), t01 = zaxpby(Rb.s, m00, Rb.c, u0);
-                const Z t10 = zaxpby(Rb.c, m10, -Rb.s, u1), t11 = zaxpby(Rb.s, m10, Rb.c, u1);
-                const Z v0 = zcmul_f(Ra.e, t10), v1 = zcmul_f(Ra.e, t11);
-                pk_set(P, rb, pa, pb, zaxpby(Ra.c, t00, -Ra.s, v0));
-                if (qb_ok) pk_set(P, rb, pa, qb, zaxpby(Ra.c, t01, -Ra.s, v1));
-                if (qa_ok) pk_set(P, rb, qa, pb, zaxpby(Ra.s, t00, Ra.c, v0));
-                if (qa_ok && qb_ok) pk_set(P, rb, qa, qb, zaxpby(Ra.s, t01, Ra.c, v1));
+                const Z m00 = get(pa, pb);
+                const Z m01 = qb_ok ? get(pa, qb) : zero;
+                const Z m10 = qa_ok ? get(qa, pb) : zero;
+                const Z m11 = (qa_ok && qb_ok) ? get(qa, qb) : zero;
+                const Z u0 = zmul_f(eb, m01), u1 = zmul_f(eb, m11);
+                const Z t00 = zaxpby(rbr.c, m00, -rbr.s, u0), t01 = zaxpby(rbr.s, m00, rbr.c, u0);
+                const Z t10 = zaxpby(rbr.c, m10, -rbr.s, u1), t11 = zaxpby(rbr.s, m10, rbr.c, u1);
+                const Z v0 = zcmul_f(ea, t10), v1 = zcmul_f(ea, t11);
+                put(pa, pb, zaxpby(ra.c, t00, -ra.s, v0));
+                if (qb_ok) put(pa, qb, zaxpby(ra.c, t01, -ra.s, v1));
+                if (qa_ok) put(qa, pb, zaxpby(ra.s, t00, ra.c, v0));
+                if (qa_ok && qb_ok) put(qa, qb, zaxpby(ra.s, t01, ra.c, v1));
             }
             __syncthreads();
         }
