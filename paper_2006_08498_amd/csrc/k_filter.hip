@@ -108,7 +108,11 @@ namespace {
 // CU = waves per SIMD of the tile's register budget (hipcc resource usage
 // for gfx950); a round of `slots` workgroups runs concurrently, and a
 // workgroup's time falls as 1/splits.  Splitting costs a partial-sum pass
-// (2 * splits * N * n * 16 bytes), charged at 2% per split.
+// (2 * splits * N * n * 16 bytes), charged at 2% per split.  A split keeps
+// at least 512 columns of H, 128 below N = 8192: there the row blocks alone
+// fill a third of the CUs or less (N = 2000, 32 row blocks: 3 splits under
+// the 512 floor, 7 under 128, and a D + K N = 2000 solve 19.6 -> 15.5 ms;
+// 5 or 14 splits were both slower, 17.0 ms).
 FilterPlan plan_blocks(int64_t N, int wn, int cb) {
     static const int occ[11] = {0, 3, 2, 2, 2, 3, 2, 2, 2, 1, 1};
     FilterPlan p{};
@@ -120,7 +124,7 @@ FilterPlan plan_blocks(int64_t N, int wn, int cb) {
     double best = 1e300;
     int bests = 1;
     for (int sp = 1; sp <= 16; ++sp) {
-        if (sp > 1 && N / sp < 512) break;
+        if (sp > 1 && N / sp < (N < 8192 ? 128 : 512)) break;
         const double rounds = (double)((units * sp + slots - 1) / slots);
         const double cost = rounds / sp + 0.02 * (sp - 1);
         if (cost < best - 1e-12) {
