@@ -466,28 +466,37 @@ struct Rot {
     bool active;
 };
 
-__device__ Rot make_rot(const Z *A, int n, int p, int q) {
-    Rot R{1.0, 0.0, Z{1.0, 0.0}, 0.0, 0.0, false};
-    const double app = A[(int64_t)p * n + p].x;   // p < n always
-    R.dp = app;
-    if (q >= n) return R;      // phantom partner (n odd): identity
-    const double aqq = A[(int64_t)q * n + q].x;
-    const Z apq = A[(int64_t)p * n + q];
-    const double x = sqrt(apq.x * apq.x + apq.y * apq.y);
-    R.dp = app;
-    R.dq = aqq;
+// The rotation for the pivot pair (p, q) from a_pp, a_qq and a_pq: the
+// phase e = conj(a_pq)/|a_pq| makes the pair real, then t = tan(theta) is
+// the root of smaller modulus of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp)
+// / (2 |a_pq|), with c = 1/sqrt(1 + t^2) and s = t c (Golub & Van Loan
+// Alg. 8.5.1 after the phase).  A round waits on this dependent chain, so
+// 1/|a_pq| and c come from reciprocal square roots: one square root and one
+// division remain (against three of each in the textbook form).  Returns
+// the identity (active = false) when a_pq is zero or negligible.
+__device__ __forceinline__ Rot rot_from(double app, double aqq, Z apq) {
+    Rot R{1.0, 0.0, Z{1.0, 0.0}, app, aqq, false};
+    const double s2 = apq.x * apq.x + apq.y * apq.y;
+    const double r = rsqrt(s2);   // 1/|a_pq| (inf for 0, then x is NaN)
+    const double x = s2 * r;
     if (!(x > 1e-300) || x <= 1e-18 * (fabs(app) + fabs(aqq))) return R;
-    R.e = Z{apq.x / x, -apq.y / x};
-    const double tau = (aqq - app) / (2.0 * x);
+    R.e = Z{apq.x * r, -apq.y * r};
+    const double tau = (aqq - app) * (0.5 * r);
     double t;
     if (fabs(tau) > 1e150) t = 0.5 / tau;
-    else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    R.c = 1.0 / sqrt(1.0 + t * t);
+    else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
+    R.c = rsqrt(fma(t, t, 1.0));
     R.s = t * R.c;
     R.dp = app - t * x;
     R.dq = aqq + t * x;
     R.active = true;
     return R;
+}
+
+__device__ Rot make_rot(const Z *A, int n, int p, int q) {
+    const double app = A[(int64_t)p * n + p].x;   // p < n always
+    if (q >= n) return Rot{1.0, 0.0, Z{1.0, 0.0}, app, 0.0, false};   // phantom partner (n odd)
+    return rot_from(app, A[(int64_t)q * n + q].x, A[(int64_t)p * n + q]);
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_round(
@@ -783,26 +792,9 @@ __device__ __forceinline__ Z zaxpby(double c, Z x, double s, Z y) {
 
 // make_rot on the packed matrix (p < q).
 __device__ Rot make_rot_packed(const Z *P, int n, int p, int q) {
-    Rot R{1.0, 0.0, Z{1.0, 0.0}, 0.0, 0.0, false};
     const double app = P[pk_idx(p, p, n)].x;
-    R.dp = app;
-    if (q >= n) return R;
-    const double aqq = P[pk_idx(q, q, n)].x;
-    const Z apq = P[pk_idx(p, q, n)];
-    const double x = sqrt(apq.x * apq.x + apq.y * apq.y);
-    R.dq = aqq;
-    if (!(x > 1e-300) || x <= 1e-18 * (fabs(app) + fabs(aqq))) return R;
-    R.e = Z{apq.x / x, -apq.y / x};
-    const double tau = (aqq - app) / (2.0 * x);
-    double t;
-    if (fabs(tau) > 1e150) t = 0.5 / tau;
-    else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    R.c = 1.0 / sqrt(1.0 + t * t);
-    R.s = t * R.c;
-    R.dp = app - t * x;
-    R.dq = aqq + t * x;
-    R.active = true;
-    return R;
+    if (q >= n) return Rot{1.0, 0.0, Z{1.0, 0.0}, app, 0.0, false};
+    return rot_from(app, P[pk_idx(q, q, n)].x, P[pk_idx(p, q, n)]);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
