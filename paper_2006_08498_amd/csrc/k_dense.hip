@@ -30,10 +30,11 @@ __device__ __forceinline__ Z zsub(Z a, Z b) { return Z{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ Z zscale(Z a, double s) { return Z{a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------- CholeskyQR
-// CholeskyQR factor, one workgroup of 8 waves: G (n x n Hermitian,
-// row-major, n <= 1024, not modified) -> B = D L^{-H} (upper triangular,
-// row-major) with L the lower Cholesky factor of W = D G D + shift I and
-// D = diag(G)^{-1/2}, so that V <- V B orthonormalises.  *info = 0, or
+// CholeskyQR factor, two launches: k_chol_prep writes W = D G D + shift I
+// (one workgroup per 16 x 16 tile), then one workgroup of 8 waves factors
+// it: G (n x n Hermitian, row-major, n <= 1024, not modified) -> B =
+// D L^{-H} (upper triangular, row-major) with L the lower Cholesky factor
+// of W and D = diag(G)^{-1/2}, so that V <- V B orthonormalises.  *info = 0, or
 // j + 1 for the first non-positive (or non-finite) pivot j (then B is not
 // complete).
 //
