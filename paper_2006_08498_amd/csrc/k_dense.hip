@@ -1259,11 +1259,13 @@ void jacobi_eig(Z *A, int n, double *w, Z *Y, Z *work, double *hwork,
                 hipStream_t s, JacobiGraphs *graphs, int *hstatus) {
     if (n <= kJacobiLds) {
         // One launch, no host round trip per sweep; the status word lives
-        // in the (otherwise unused) work buffer.  At most 8 waves, so that
-        // the launch fits beside other kernels.
+        // in the (otherwise unused) work buffer.  8 waves at every order: a
+        // round's work is what bounds it (n = 30: 1 wave 1057 us, 2 waves
+        // 623, 4 waves 380, 8 waves 340 per eigensolve), and no more, so
+        // that the launch fits beside other kernels.
         const int max_sweeps = jacobi_max_sweeps();
         int *dstatus = reinterpret_cast<int *>(work);
-        const int threads = n <= 32 ? 256 : 512;
+        const int threads = 512;
         hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(threads), 0, s, (const Z *)A, n,
                            max_sweeps, w, Y, dstatus);
         check_launch("k_jacobi_small");
